@@ -1,0 +1,177 @@
+/*
+ * blnfft.h — C ABI of an MI355X (gfx950) library for the NFFT-like procedure for
+ * bandlimited functions of Kircheis & Potts, "Nonequispaced fast Fourier transforms for
+ * bandlimited functions" (Algorithm 4.2), with the classical NFFT (Algorithm 2.1) beside it.
+ *
+ * Problem (Section 4, opening paragraph and Algorithm 4.2, input/output): given samples
+ * fhat(k), k in I_M = [-M/2, M/2)^d, of the Fourier transform (1.1) of a bandlimited
+ * function f, compute f_j ~ f(x_j) at nonequispaced nodes x_j in [-1/2, 1/2)^d.
+ *
+ * Conventions used by every call
+ * ------------------------------
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or equivalent, on the device the
+ *    plan was created on).  The caller owns them; the library never frees them.
+ *  - Precision: BL_F64 uses double / interleaved double2 complex.  BL_F32 and BL_F32C use
+ *    float / interleaved float2 complex for every input and output.
+ *  - fhat is an M^d complex array, row-major (last dimension fastest); array index i_t
+ *    holds frequency k_t = i_t - M/2.
+ *  - Nodes x are an N x d real array, row-major (x[j*d + t]), each coordinate in [-1/2, 1/2).
+ *  - f and g are length-N complex arrays in the caller's node order.
+ *  - Samples on the oversampled grid (theta) are an L^d complex array, row-major, index
+ *    i_t holding grid point l_t = i_t - L/2 (the centred order of I_L).
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.  Every
+ *    compute call is asynchronous on the plan's stream unless stated otherwise.
+ *  - Errors: every call returns a bl_status; nothing throws across the ABI.  On error
+ *    bl_last_error() returns a thread-local message.  Invalid arguments are rejected
+ *    before any allocation or launch.
+ *  - A plan is used from one host thread and one stream at a time.
+ */
+#ifndef BLNFFT_H
+#define BLNFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BL_OK = 0,
+    BL_EINVAL = 1,        /* invalid argument (size, pointer, parameter range)          */
+    BL_EDOMAIN = 2,       /* a node is NaN/Inf or outside [-1/2, 1/2)^d                  */
+    BL_ENOMEM = 3,        /* device or host allocation failed                           */
+    BL_EDEVICE = 4,       /* a HIP runtime call failed                                   */
+    BL_ESTATE = 5,        /* call out of order (e.g. forward before set_nodes)          */
+    BL_EUNSUPPORTED = 6   /* valid but not implemented (e.g. m above the kernel range)  */
+} bl_status;
+
+typedef enum {
+    BL_WIN_SINH = 0,      /* sinh-type window, eq. (3.4)                                */
+    BL_WIN_CKB = 1        /* continuous Kaiser-Bessel window, Remark 3.1                */
+} bl_window;
+
+typedef enum {
+    BL_SHANNON = 0,       /* Algorithm 4.2: psihat deconvolution, regularized-sinc sums  */
+    BL_NFFT = 1           /* Algorithm 2.1 with M_sigma = L: phihat deconvolution,
+                             periodic window sums over I_{L,m}(x_j), eq. (2.5)          */
+} bl_method;
+
+typedef enum {
+    BL_F64 = 0,           /* everything in double                                       */
+    BL_F32 = 1,           /* float data and arithmetic, FP64-derived twiddles/factors   */
+    BL_F32C = 2           /* float inputs, outputs and grid of samples; the FFT passes
+                             compute in double with double intermediates (one rounding,
+                             at the store of the grid); short sums with float weights and
+                             compensated (error-free product + two-sum) accumulation   */
+} bl_precision;
+
+typedef struct bl_plan_s* bl_plan;
+typedef struct bl_batch_s* bl_batch;
+
+typedef struct {
+    int64_t n_nodes;          /* N of the last bl_set_nodes                                */
+    int64_t n_outside;        /* nodes outside the truncated domain [-1/2+m/L, 1/2-m/L)^d  */
+    int64_t n_chunks;         /* work items of the short-sum kernels                       */
+    int64_t tile[3];          /* grid cells per tile edge, per dimension                   */
+    int64_t chunk_cap;        /* max nodes per work item                                   */
+    int64_t workspace_bytes;  /* device memory owned by the plan                           */
+    double beta;              /* window shape parameter in use                             */
+} bl_stats;
+
+/* Create a plan.  Algorithm 4.2 step 0a (psihat(k), k in I_M; eq. (4.9)) or Algorithm 2.1
+ * step 0a (phihat(k)) is computed here on the host in double precision.
+ *   d      : 1, 2 or 3.
+ *   M      : bandwidth per dimension, even, >= 2 (I_M, Section 1).
+ *   L      : oversampled grid per dimension, even, L >= M (Algorithm 4.2, L = M(1+lambda)).
+ *   m      : truncation, 1 <= m and 2m < L; this build's kernels take 2 <= m <= 8
+ *            (BL_EUNSUPPORTED otherwise).
+ *   win    : window (Remark 3.1).
+ *   beta   : window parameter; beta <= 0 picks the default: pi*m*(L-M)/L for BL_SHANNON,
+ *            2*pi*m*(1 - M/(2L)) for BL_NFFT.
+ *   method : BL_SHANNON or BL_NFFT.
+ *   prec   : BL_F64, BL_F32 or BL_F32C.
+ *   stream : hipStream_t (as void*) for every later call.
+ * Synchronous.  Allocates the plan's device workspace (grid of L^d complex samples,
+ * FFT intermediates, tables).  On error *out is set to NULL and nothing is allocated. */
+bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_window win,
+                         double beta, bl_method method, bl_precision prec, void* stream);
+
+/* Bind nodes (Algorithm 4.2 step 0b, realised as binning: nodes are sorted into grid tiles
+ * so that the short sums of step 3 read a tile of samples from on-chip memory).
+ *   N     : number of nodes, N >= 0.
+ *   x_dev : N x d nodes, row-major, in the plan's real type; each coordinate must lie in
+ *           [-1/2, 1/2).  The library copies them (sorted), so x_dev may be reused
+ *           after this call returns.
+ * Synchronizes with the plan's stream once.  Returns BL_EDOMAIN if any coordinate is NaN,
+ * infinite or outside [-1/2, 1/2) (the plan then holds no nodes). */
+bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev);
+
+/* Forward transform, Algorithm 4.2 steps 1-3 (or Algorithm 2.1 steps 1-3):
+ *   step 1: thetahat(k) = fhat(k) / psihat(k) on I_M, 0 on I_L \ I_M;
+ *   step 2: theta_l = L^-d sum_{k in I_L} thetahat(k) e^{2 pi i k l / L}   (4.7);
+ *   step 3: f_j = sum_{l in J_{L,m}(x_j)} theta_l psi(x_j - l/L)           (4.8),
+ * with theta_l = 0 for l outside I_L (zero-extended sum; BL_NFFT wraps periodically).
+ *   fhat_dev : M^d complex (input).   f_dev : N complex (output, overwritten).
+ * Asynchronous.  Keeps theta for bl_grad_x / bl_get_theta. */
+bl_status bl_forward(bl_plan plan, const void* fhat_dev, void* f_dev);
+
+/* Regularized Shannon sampling formula (3.5) truncated to I_L: evaluate step 3 alone on
+ * given samples theta_dev (L^d complex, centred order) at the bound nodes.
+ *   f_dev : N complex (output).  Asynchronous. */
+bl_status bl_interpolate(bl_plan plan, const void* theta_dev, void* f_dev);
+
+/* Copy the samples theta_l, l in I_L, of the last bl_forward to theta_dev (L^d complex,
+ * centred order).  BL_ESTATE before any forward.  Asynchronous. */
+bl_status bl_get_theta(bl_plan plan, void* theta_dev);
+
+/* Adjoint of the factorisation (4.11): fhat_out = D_psihat^H F^H Psi^T g  (BL_SHANNON), or
+ * D^H F^H B^T g (BL_NFFT).  D is real; F^H uses e^{-2 pi i k l / L}.
+ *   g_dev : N complex (input).   fhat_dev : M^d complex (output, overwritten).
+ * Asynchronous. */
+bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev);
+
+/* Gradient with respect to the nodes: gx[j*d + t] = Re( conj(g_j) * d f_j / d x_jt ),
+ * f from the last bl_forward (BL_SHANNON only).  With g = 2(f - y) this is the gradient
+ * of sum_j |f_j - y_j|^2.   g_dev : N complex.  gx_dev : N x d real (output).
+ * BL_ESTATE if no forward has run since the last bl_set_nodes.  Asynchronous. */
+bl_status bl_grad_x(bl_plan plan, const void* g_dev, void* gx_dev);
+
+/* Plan statistics.  Synchronous with respect to host state only. */
+bl_status bl_plan_stats(bl_plan plan, bl_stats* out);
+
+/* Destroy a plan (synchronizes its stream, frees its workspace).  NULL is accepted. */
+bl_status bl_plan_destroy(bl_plan plan);
+
+/* Host-only: the window transform used for the deconvolution factors, by the library's
+ * own quadrature.  out[i] = psihat(v[i]) for BL_SHANNON (Algorithm 4.2 step 0a, the
+ * transform (3.1) of psi in (4.2)) or phihat(v[i]) for BL_NFFT (Algorithm 2.1 step 0a),
+ * univariate.  beta <= 0 picks the default for (M, L, m, method).  Needs no GPU. */
+bl_status bl_window_transform(bl_window win, bl_method method, int64_t M, int64_t L, int m,
+                              double beta, int64_t n, const double* v, double* out);
+
+/* Batched d = 1 transforms (Algorithm 4.2, BL_SHANNON, sinh window, default beta) of
+ * `count` independent instances with their own (M_i, L_i, m_i, N_i), executed together.
+ *   M, L, m, N : host arrays of length count (same rules as bl_plan_create per instance).
+ *   prec       : BL_F32, BL_F32C or BL_F64.
+ * Packed device buffers: instance i's fhat occupies sum_{i'<i} M_i' .. complex elements,
+ * its nodes and outputs sum_{i'<i} N_i' ...  Synchronous. */
+bl_status bl_batch_create(bl_batch* out, int count, const int64_t* M, const int64_t* L,
+                          const int* m, const int64_t* N, bl_precision prec, void* stream);
+/* Bind the packed nodes (sum N_i reals).  Synchronizes once; BL_EDOMAIN as bl_set_nodes. */
+bl_status bl_batch_set_nodes(bl_batch batch, const void* x_dev);
+/* Forward transform of every instance: packed fhat in, packed f out.  Asynchronous. */
+bl_status bl_batch_forward(bl_batch batch, const void* fhat_dev, void* f_dev);
+bl_status bl_batch_destroy(bl_batch batch);
+
+/* Status text (static storage) and the calling thread's last error message. */
+const char* bl_status_string(bl_status s);
+const char* bl_last_error(void);
+
+/* Library version string (static storage). */
+const char* bl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLNFFT_H */

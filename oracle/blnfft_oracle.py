@@ -434,10 +434,10 @@ def grad_x_shannon(fhat: np.ndarray, G: np.ndarray, x: np.ndarray, L: int, m: in
     if beta is None:
         beta = default_beta(M, L, m, "shannon")
     theta = inverse_fft_step(deconvolve_pad(fhat, L, m, beta, win, "shannon"))
-    return _grad_x_from_theta(theta, G, x, L, m, beta, win, chunk)
+    return grad_x_from_theta(theta, G, x, L, m, beta, win, chunk)
 
 
-def _grad_x_from_theta(theta, G, x, L, m, beta, win, chunk=65536):
+def grad_x_from_theta(theta, G, x, L, m, beta, win, chunk=65536):
     d = theta.ndim
     N = x.shape[0]
     pad = m + 1

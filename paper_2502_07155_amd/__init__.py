@@ -1,0 +1,10 @@
+"""MI355X (gfx950) library for the NFFT-like procedure for bandlimited functions
+(Kircheis & Potts, Algorithm 4.2) and the classical NFFT (Algorithm 2.1).
+
+The transforms run in hand-written HIP kernels of ``libblnfft.so`` behind a C ABI
+(``include/blnfft.h``); this package only marshals torch tensors to that ABI.
+"""
+from ._lib import BLNFFTError, EXPORTS, LIB_PATH, load  # noqa: F401
+from .plan import Plan, window_transform  # noqa: F401
+
+__all__ = ["Plan", "window_transform", "BLNFFTError", "load", "LIB_PATH", "EXPORTS"]

@@ -1,0 +1,348 @@
+// C ABI of the blnfft library: validation, plan lifecycle and call dispatch.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "blnfft_internal.h"
+
+struct bl_plan_s {
+    bl::Plan p;
+};
+
+namespace bl {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+const std::string& last_error() { return g_err; }
+
+size_t gather_lds_bytes(const Plan& p);
+
+namespace {
+
+bl_status fail(bl_status s, const std::string& msg) {
+    set_error(msg);
+    return s;
+}
+
+int64_t ipow(int64_t b, int e) {
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+template <typename T>
+bl_status dev_alloc(T** ptr, size_t bytes, size_t* total) {
+    *ptr = nullptr;
+    if (bytes == 0) return BL_OK;
+    if (const char* f = std::getenv("BL_TEST_FAIL_ALLOC")) {
+        if (f[0] == '1') return fail(BL_ENOMEM, "allocation refused by BL_TEST_FAIL_ALLOC");
+    }
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(ptr), bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? BL_ENOMEM : BL_EDEVICE,
+                    std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    *total += bytes;
+    return BL_OK;
+}
+
+void free_nodes(Plan& p) {
+    hipFree(p.d_xs);
+    hipFree(p.d_perm);
+    hipFree(p.d_node_tile);
+    hipFree(p.d_chunks);
+    p.d_xs = nullptr;
+    p.d_perm = nullptr;
+    p.d_node_tile = nullptr;
+    p.d_chunks = nullptr;
+    p.N_cap = 0;
+    p.chunk_alloc = 0;
+}
+
+void free_plan(Plan& p) {
+    free_nodes(p);
+    hipFree(p.d_deconv);
+    hipFree(p.d_tw64);
+    hipFree(p.d_tw32);
+    hipFree(p.d_bufA);
+    hipFree(p.d_bufB);
+    hipFree(p.d_grid);
+    hipFree(p.d_sgrid);
+    hipFree(p.d_tile_count);
+    hipFree(p.d_tile_offset);
+    hipFree(p.d_tile_cursor);
+    hipFree(p.d_chunk_offset);
+    hipFree(p.d_flags);
+}
+
+// Tile edge per dimension for the short-sum kernels: the staged tile plus halo must fit
+// the LDS budget.
+void choose_tiles(Plan& p) {
+    const int d = p.d;
+    const size_t c = p.cplx_size();
+    const size_t budget = 64 * 1024;
+    int T;
+    if (d == 1) T = 512;
+    else if (d == 2) T = 16;
+    else T = 8;
+    auto bytes = [&](int t) {
+        size_t e = 1;
+        for (int k = 0; k < d; ++k) e *= size_t(t + 2 * p.m - 1);
+        return e * c;
+    };
+    while (T > 1 && bytes(T) > budget) T /= 2;
+    if (T > p.L) T = int(p.L);
+    p.ntiles = 1;
+    for (int t = 0; t < 3; ++t) {
+        p.tile[t] = t < d ? T : 1;
+        p.tiles_per_dim[t] = t < d ? int((p.L + T - 1) / T) : 1;
+        p.ntiles *= p.tiles_per_dim[t];
+    }
+    p.chunk_cap = 1024;
+}
+
+bl_status check_plan(bl_plan plan) {
+    if (!plan) return fail(BL_EINVAL, "plan is NULL");
+    BL_HIP(hipSetDevice(plan->p.device));
+    return BL_OK;
+}
+
+}  // namespace
+}  // namespace bl
+
+using namespace bl;
+
+extern "C" {
+
+const char* bl_status_string(bl_status s) {
+    switch (s) {
+        case BL_OK: return "BL_OK";
+        case BL_EINVAL: return "BL_EINVAL: invalid argument";
+        case BL_EDOMAIN: return "BL_EDOMAIN: node outside [-1/2, 1/2)^d or not finite";
+        case BL_ENOMEM: return "BL_ENOMEM: out of memory";
+        case BL_EDEVICE: return "BL_EDEVICE: HIP runtime error";
+        case BL_ESTATE: return "BL_ESTATE: call out of order";
+        case BL_EUNSUPPORTED: return "BL_EUNSUPPORTED: not supported by this build";
+    }
+    return "unknown bl_status";
+}
+
+const char* bl_last_error(void) { return last_error().c_str(); }
+
+const char* bl_version(void) { return "blnfft 0.1 (gfx950)"; }
+
+bl_status bl_window_transform(bl_window win, bl_method method, int64_t M, int64_t L, int m,
+                              double beta, int64_t n, const double* v, double* out) {
+    if (win != BL_WIN_SINH && win != BL_WIN_CKB) return fail(BL_EINVAL, "unknown window");
+    if (method != BL_SHANNON && method != BL_NFFT) return fail(BL_EINVAL, "unknown method");
+    if (L < 2 || m < 1 || 2 * int64_t(m) >= L || M < 2 || M > L)
+        return fail(BL_EINVAL, "need 2 <= M <= L and 1 <= m, 2m < L");
+    if (n < 0 || (n > 0 && (!v || !out))) return fail(BL_EINVAL, "bad array arguments");
+    if (!(beta > 0.0)) beta = default_beta(M, L, m, method);
+    if (!std::isfinite(beta)) return fail(BL_EINVAL, "beta not finite");
+    for (int64_t i = 0; i < n; ++i) out[i] = window_transform(win, method, L, m, beta, v[i]);
+    return BL_OK;
+}
+
+bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_window win,
+                         double beta, bl_method method, bl_precision prec, void* stream) {
+    if (!out) return fail(BL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (d < 1 || d > 3) return fail(BL_EINVAL, "d must be 1, 2 or 3");
+    if (M < 2 || (M % 2) != 0) return fail(BL_EINVAL, "M must be even and >= 2");
+    if (L < M || (L % 2) != 0) return fail(BL_EINVAL, "L must be even and >= M");
+    if (m < 1 || 2 * int64_t(m) >= L) return fail(BL_EINVAL, "need 1 <= m and 2m < L");
+    if (win != BL_WIN_SINH && win != BL_WIN_CKB) return fail(BL_EINVAL, "unknown window");
+    if (method != BL_SHANNON && method != BL_NFFT) return fail(BL_EINVAL, "unknown method");
+    if (prec != BL_F64 && prec != BL_F32 && prec != BL_F32C) return fail(BL_EINVAL, "unknown precision");
+    if (std::isnan(beta) || std::isinf(beta)) return fail(BL_EINVAL, "beta not finite");
+    if (m < kMinM || m > kMaxM)
+        return fail(BL_EUNSUPPORTED, "compiled short-sum kernels cover 2 <= m <= 8");
+    if (win != BL_WIN_SINH) return fail(BL_EUNSUPPORTED, "GPU kernels implement the sinh-type window");
+    FftFactors fac;
+    if (L > (1 << 30) || !factor_length(int(L), &fac))
+        return fail(BL_EUNSUPPORTED, "per-plan FFT needs L a power of two");
+    // one line of L complex values per LDS pass: <= 1024 threads in FP32, <= 512 in FP64
+    const int64_t Lmax = (prec == BL_F32) ? 16384 : 8192;
+    if (L > Lmax) return fail(BL_EUNSUPPORTED, "L above the LDS FFT limit for this precision");
+    const int64_t grid = ipow(L, d);
+    if (grid > (int64_t(1) << 31)) return fail(BL_EUNSUPPORTED, "grid L^d too large");
+
+    bl_plan_s* h = new (std::nothrow) bl_plan_s();
+    if (!h) return fail(BL_ENOMEM, "host allocation failed");
+    Plan& p = h->p;
+    p.d = d;
+    p.M = M;
+    p.L = L;
+    p.m = m;
+    p.win = win;
+    p.method = method;
+    p.prec = prec;
+    p.beta = (beta > 0.0) ? beta : default_beta(M, L, m, method);
+    p.stream = static_cast<hipStream_t>(stream);
+    p.fac = fac;
+    auto cleanup = [&](bl_status s) {
+        free_plan(p);
+        delete h;
+        return s;
+    };
+    if (hipGetDevice(&p.device) != hipSuccess) return cleanup(fail(BL_EDEVICE, "hipGetDevice failed"));
+
+    // Step 0a: per-dimension factors 1/(L hat1(k)), k = i - M/2, in FP64 (4.9) / (2.2).
+    std::vector<double> fac_h(M);
+    for (int64_t i = 0; i < M; ++i) {
+        double hv = window_transform(win, method, L, m, p.beta, double(i - M / 2));
+        if (!(std::fabs(hv) > 0.0) || !std::isfinite(hv))
+            return cleanup(fail(BL_EINVAL, "window transform vanishes on I_M for this beta"));
+        fac_h[i] = 1.0 / (double(L) * hv);
+    }
+    std::vector<double> tw;
+    twiddles(L, &tw);
+    std::vector<float> tw32(tw.size());
+    for (size_t i = 0; i < tw.size(); ++i) tw32[i] = float(tw[i]);
+
+    size_t total = 0;
+    bl_status s;
+    const size_t c = p.cplx_size();
+    // FFT intermediates: forward passes produce M^{d-1} L and M^{d-2} L^2 elements; the
+    // adjoint passes L^{d-1} M and L^{d-2} M^2.
+    int64_t A = 0, B = 0;
+    if (d >= 2) A = std::max(ipow(M, d - 1) * L, ipow(L, d - 1) * M);
+    if (d >= 3) B = std::max(ipow(M, d - 2) * L * L, ipow(L, d - 2) * M * M);
+    if ((s = dev_alloc(&p.d_deconv, sizeof(double) * M, &total)) != BL_OK) return cleanup(s);
+    if ((s = dev_alloc(&p.d_tw64, sizeof(double) * 2 * L, &total)) != BL_OK) return cleanup(s);
+    if ((s = dev_alloc(&p.d_tw32, sizeof(float) * 2 * L, &total)) != BL_OK) return cleanup(s);
+    if ((s = dev_alloc(&p.d_grid, size_t(grid) * c, &total)) != BL_OK) return cleanup(s);
+    // F32C keeps the FFT pass intermediates in double.
+    const size_t ci = (prec == BL_F32) ? c : 16;
+    if ((s = dev_alloc(&p.d_bufA, size_t(A) * ci, &total)) != BL_OK) return cleanup(s);
+    if ((s = dev_alloc(&p.d_bufB, size_t(B) * ci, &total)) != BL_OK) return cleanup(s);
+    choose_tiles(p);
+    if ((s = dev_alloc(&p.d_tile_count, sizeof(int32_t) * p.ntiles, &total)) != BL_OK) return cleanup(s);
+    if ((s = dev_alloc(&p.d_tile_offset, sizeof(int32_t) * p.ntiles, &total)) != BL_OK) return cleanup(s);
+    if ((s = dev_alloc(&p.d_tile_cursor, sizeof(int32_t) * p.ntiles, &total)) != BL_OK) return cleanup(s);
+    if ((s = dev_alloc(&p.d_chunk_offset, sizeof(int32_t) * p.ntiles, &total)) != BL_OK) return cleanup(s);
+    if ((s = dev_alloc(&p.d_flags, sizeof(unsigned long long) * 4, &total)) != BL_OK) return cleanup(s);
+    p.workspace_bytes = total;
+
+    hipError_t e = hipMemcpyAsync(p.d_deconv, fac_h.data(), sizeof(double) * M, hipMemcpyHostToDevice, p.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p.d_tw64, tw.data(), sizeof(double) * 2 * L, hipMemcpyHostToDevice, p.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p.d_tw32, tw32.data(), sizeof(float) * 2 * L, hipMemcpyHostToDevice, p.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+    if (e != hipSuccess) return cleanup(fail(BL_EDEVICE, std::string("table upload: ") + hipGetErrorString(e)));
+    *out = h;
+    return BL_OK;
+}
+
+bl_status bl_plan_destroy(bl_plan plan) {
+    if (!plan) return BL_OK;
+    hipSetDevice(plan->p.device);
+    hipStreamSynchronize(plan->p.stream);
+    free_plan(plan->p);
+    delete plan;
+    return BL_OK;
+}
+
+bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev) {
+    BL_TRY(check_plan(plan));
+    Plan& p = plan->p;
+    if (N < 0 || N > int64_t(0x7fffffff)) return fail(BL_EINVAL, "N out of range");
+    if (N > 0 && !x_dev) return fail(BL_EINVAL, "x_dev is NULL");
+    p.have_nodes = false;
+    p.have_theta = false;
+    p.N = 0;
+    const int64_t chunk_bound = N / p.chunk_cap + p.ntiles + 1;
+    if (N > p.N_cap || chunk_bound > p.chunk_alloc) {
+        BL_HIP(hipStreamSynchronize(p.stream));
+        free_nodes(p);
+        size_t extra = 0;
+        const int64_t ncap = std::max<int64_t>(N, 1);
+        bl_status s;
+        if ((s = dev_alloc(&p.d_xs, size_t(ncap) * p.d * p.real_size(), &extra)) != BL_OK) return s;
+        if ((s = dev_alloc(&p.d_perm, sizeof(int32_t) * ncap, &extra)) != BL_OK) return s;
+        if ((s = dev_alloc(&p.d_node_tile, sizeof(int32_t) * ncap, &extra)) != BL_OK) return s;
+        const int64_t cb = ncap / p.chunk_cap + p.ntiles + 1;
+        if ((s = dev_alloc(&p.d_chunks, sizeof(int4) * cb, &extra)) != BL_OK) return s;
+        p.N_cap = ncap;
+        p.chunk_alloc = cb;
+    }
+    BL_TRY(launch_binning(p, x_dev, N));
+    p.N = N;
+    p.have_nodes = true;
+    return BL_OK;
+}
+
+bl_status bl_forward(bl_plan plan, const void* fhat_dev, void* f_dev) {
+    BL_TRY(check_plan(plan));
+    Plan& p = plan->p;
+    if (!p.have_nodes) return fail(BL_ESTATE, "bl_set_nodes must succeed before bl_forward");
+    if (!fhat_dev || (p.N > 0 && !f_dev)) return fail(BL_EINVAL, "NULL buffer");
+    BL_TRY(launch_forward_fft(p, fhat_dev));
+    p.have_theta = true;
+    return launch_gather(p, p.d_grid, f_dev);
+}
+
+bl_status bl_interpolate(bl_plan plan, const void* theta_dev, void* f_dev) {
+    BL_TRY(check_plan(plan));
+    Plan& p = plan->p;
+    if (!p.have_nodes) return fail(BL_ESTATE, "bl_set_nodes must succeed before bl_interpolate");
+    if (!theta_dev || (p.N > 0 && !f_dev)) return fail(BL_EINVAL, "NULL buffer");
+    return launch_gather(p, theta_dev, f_dev);
+}
+
+bl_status bl_get_theta(bl_plan plan, void* theta_dev) {
+    BL_TRY(check_plan(plan));
+    Plan& p = plan->p;
+    if (!p.have_theta) return fail(BL_ESTATE, "no forward transform has run");
+    if (!theta_dev) return fail(BL_EINVAL, "NULL buffer");
+    BL_HIP(hipMemcpyAsync(theta_dev, p.d_grid, size_t(p.grid_elems()) * p.cplx_size(),
+                          hipMemcpyDeviceToDevice, p.stream));
+    return BL_OK;
+}
+
+bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev) {
+    BL_TRY(check_plan(plan));
+    Plan& p = plan->p;
+    if (!p.have_nodes) return fail(BL_ESTATE, "bl_set_nodes must succeed before bl_adjoint");
+    if (!fhat_dev || (p.N > 0 && !g_dev)) return fail(BL_EINVAL, "NULL buffer");
+    if (!p.d_sgrid) {
+        size_t extra = 0;
+        BL_HIP(hipStreamSynchronize(p.stream));
+        BL_TRY(dev_alloc(&p.d_sgrid, size_t(p.grid_elems()) * p.cplx_size(), &extra));
+        p.workspace_bytes += extra;
+    }
+    BL_TRY(launch_spread(p, g_dev, p.d_sgrid));
+    return launch_adjoint_fft(p, p.d_sgrid, fhat_dev);
+}
+
+bl_status bl_grad_x(bl_plan plan, const void* g_dev, void* gx_dev) {
+    BL_TRY(check_plan(plan));
+    Plan& p = plan->p;
+    if (p.method != BL_SHANNON) return fail(BL_EUNSUPPORTED, "grad_x is implemented for BL_SHANNON");
+    if (!p.have_theta) return fail(BL_ESTATE, "bl_grad_x needs the samples of a preceding bl_forward");
+    if (p.N > 0 && (!g_dev || !gx_dev)) return fail(BL_EINVAL, "NULL buffer");
+    return launch_grad_x(p, g_dev, gx_dev);
+}
+
+bl_status bl_plan_stats(bl_plan plan, bl_stats* out) {
+    if (!plan || !out) return fail(BL_EINVAL, "NULL argument");
+    const Plan& p = plan->p;
+    std::memset(out, 0, sizeof(*out));
+    out->n_nodes = p.N;
+    out->n_outside = p.n_outside;
+    out->n_chunks = p.nchunks;
+    for (int t = 0; t < 3; ++t) out->tile[t] = p.tile[t];
+    out->chunk_cap = p.chunk_cap;
+    out->workspace_bytes = int64_t(p.workspace_bytes);
+    out->beta = p.beta;
+    return BL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,144 @@
+// Internal declarations of the blnfft library (host side and kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "blnfft.h"
+
+namespace bl {
+
+// Thread-local error text for bl_last_error().
+void set_error(const std::string& msg);
+const std::string& last_error();
+
+// Return BL_EDEVICE (with the failing call's text) if a HIP call failed.
+#define BL_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            ::bl::set_error(std::string(#call) + ": " + hipGetErrorString(e_));        \
+            return e_ == hipErrorOutOfMemory ? BL_ENOMEM : BL_EDEVICE;                \
+        }                                                                             \
+    } while (0)
+
+#define BL_TRY(expr)                         \
+    do {                                     \
+        bl_status s_ = (expr);               \
+        if (s_ != BL_OK) return s_;          \
+    } while (0)
+
+constexpr int kMaxStages = 16;
+constexpr int kMinM = 2;    // truncation range of the compiled short-sum kernels
+constexpr int kMaxM = 8;
+
+// Factorisation of one FFT length into Stockham stages.
+struct FftFactors {
+    int L = 0;
+    int nstages = 0;
+    int radix[kMaxStages] = {0};
+};
+bool factor_length(int L, FftFactors* out);   // false if L has a prime factor > 7
+
+// One pass of the pruned multi-dimensional iFFT: transforms axis `axis` of an array
+// whose axes before `axis` have extent M (still in frequency), `axis` has Min inputs
+// (M) and L outputs, and axes after it have extent L (already transformed).
+struct PassShape {
+    int64_t outer = 1;   // M^axis
+    int64_t inner = 1;   // L^(d-1-axis)
+    int Min = 0;         // inputs per line (M)
+    int L = 0;           // FFT length and outputs per line
+};
+
+// Device tables and buffers owned by a plan.
+struct Plan {
+    int d = 0;
+    int64_t M = 0, L = 0;
+    int m = 0;
+    bl_window win = BL_WIN_SINH;
+    bl_method method = BL_SHANNON;
+    bl_precision prec = BL_F64;
+    double beta = 0.0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    FftFactors fac;
+    // Per-dimension deconvolution factor 1/(L * hat1(k)), k = i - M/2 (FP64, M entries).
+    double* d_deconv = nullptr;
+    // Twiddles e^{+2 pi i n / L}, n in [0, L): FP64 and FP32 copies.
+    void* d_tw64 = nullptr;
+    void* d_tw32 = nullptr;
+    // Inverse-direction twiddles for the adjoint are the conjugates; computed in kernel.
+
+    // FFT ping-pong buffers and the grid of theta (L^d complex).
+    void* d_bufA = nullptr;
+    void* d_bufB = nullptr;
+    void* d_grid = nullptr;
+    void* d_sgrid = nullptr;   // adjoint spreading target (allocated on first bl_adjoint)
+    size_t bytes_grid = 0, bytes_A = 0, bytes_B = 0;
+
+    // Nodes, sorted by tile.
+    int64_t N = 0;
+    int64_t N_cap = 0;
+    void* d_xs = nullptr;          // N x d sorted copy
+    int32_t* d_perm = nullptr;     // sorted position -> caller index
+    int32_t* d_node_tile = nullptr;
+    int tile[3] = {1, 1, 1};       // cells per tile edge
+    int tiles_per_dim[3] = {1, 1, 1};
+    int64_t ntiles = 0;
+    int chunk_cap = 1024;
+    int32_t* d_tile_count = nullptr;
+    int32_t* d_tile_offset = nullptr;
+    int32_t* d_tile_cursor = nullptr;
+    int32_t* d_chunk_offset = nullptr;
+    int4* d_chunks = nullptr;      // {tile, start, count, 0}
+    int64_t chunk_alloc = 0;
+    int64_t nchunks = 0;
+    unsigned long long* d_flags = nullptr;  // [0]: invalid nodes, [1]: outside truncated domain, [2]: chunks
+    int64_t n_outside = 0;
+
+    bool have_nodes = false;
+    bool have_theta = false;
+    size_t workspace_bytes = 0;
+
+    size_t real_size() const { return prec == BL_F64 ? 8 : 4; }
+    size_t cplx_size() const { return 2 * real_size(); }
+    int64_t grid_elems() const {
+        int64_t g = 1;
+        for (int t = 0; t < d; ++t) g *= L;
+        return g;
+    }
+    int64_t band_elems() const {
+        int64_t g = 1;
+        for (int t = 0; t < d; ++t) g *= M;
+        return g;
+    }
+};
+
+// ---- host tables (host_tables.cpp)
+double default_beta(int64_t M, int64_t L, int m, bl_method method);
+// Univariate transform of psi (shannon) or phi (nfft) at v, by the library's own
+// double-exponential quadrature.
+double window_transform(bl_window win, bl_method method, int64_t L, int m, double beta, double v);
+// e^{2 pi i n / L} for n in [0, L), correctly reduced; interleaved (re, im).
+void twiddles(int64_t L, std::vector<double>* out);
+
+// ---- kernel launchers (fft.hip, gather.hip, bin.hip)
+// Steps 1-2: deconvolve + zero-pad + iFFT, f̂ (M^d) -> grid (L^d).  `sign` = +1 forward
+// transform (inverse DFT); the adjoint path uses launch_fft_adjoint.
+bl_status launch_forward_fft(Plan& p, const void* fhat);
+// Adjoint FFT: grid (L^d, centred) -> fhat (M^d) with e^{-2 pi i k l/L} and D.
+bl_status launch_adjoint_fft(Plan& p, const void* grid, void* fhat_out);
+// Step 3 on the plan's grid (or a given theta).
+bl_status launch_gather(Plan& p, const void* theta, void* f);
+// Binning of nodes.
+bl_status launch_binning(Plan& p, const void* x, int64_t N);
+// Adjoint spreading Psi^T g (or B^T g) onto `grid` (L^d, centred), which it overwrites.
+bl_status launch_spread(Plan& p, const void* g, void* grid);
+// Node gradient from the plan's grid.
+bl_status launch_grad_x(Plan& p, const void* g, void* gx);
+
+}  // namespace bl

@@ -1,0 +1,406 @@
+// Step 3 of Algorithm 4.2 (short sums of the regularized Shannon formula, (4.8)) and of
+// Algorithm 2.1 (periodic window sums over I_{L,m}(x_j), (2.5)), plus the node binning
+// that realises step 0b.
+//
+// Binning sorts nodes by grid tile (counting sort: histogram, one-workgroup scan,
+// scatter) and cuts every tile into work chunks of at most `cap` nodes.  The short-sum
+// kernel runs one workgroup per chunk: it stages the tile's samples theta plus a halo of
+// m-1 cells below and m above in LDS, then each thread evaluates its nodes.
+//
+// For a node with L x = n + theta (n integer, theta in [0, 1)) the 2m grid points
+// l = n - m + 1 + o, o = 0..2m-1, carry every nonzero weight: the end points of
+// J_{L,m}(x) have sinc(+-m pi) phi(+-m/L) = 0.  The offset u = L x - l = theta + m - 1 - o,
+// and sin(pi u) = (-1)^{m-1-o} sin(pi theta), so one sin per node and dimension serves all
+// 2m weights; sin(pi theta) is reduced to [0, 1/2] by reflection.
+#include "blnfft_internal.h"
+#include "device_math.h"
+
+namespace bl {
+namespace {
+
+using namespace dev;
+
+// ---------------------------------------------------------------- binning kernels
+struct BinArgs {
+    const void* x;
+    int64_t N;
+    int d, L, m;
+    int tile[3];
+    int tpd[3];              // tiles per dimension
+    int32_t* node_tile;
+    int32_t* tile_count;
+    unsigned long long* flags;   // [0] invalid, [1] outside truncated domain
+};
+
+template <typename R, int D>
+__global__ void k_bin_count(BinArgs a) {
+    int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= a.N) return;
+    const R* x = static_cast<const R*>(a.x);
+    int tile = 0;
+    bool bad = false, outside = false;
+    const R lim = R(0.5) - R(a.m) / R(a.L);
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        R xt = x[j * D + t];
+        if (!(xt >= R(-0.5) && xt < R(0.5))) { bad = true; xt = R(0); }
+        if (!(xt >= -lim && xt < lim)) outside = true;
+        int n;
+        R th;
+        cell_of<R>(xt, a.L, n, th);
+        int cell = n + a.L / 2;
+        tile = tile * a.tpd[t] + cell / a.tile[t];
+    }
+    if (bad) atomicAdd(&a.flags[0], 1ull);
+    if (outside) atomicAdd(&a.flags[1], 1ull);
+    a.node_tile[j] = tile;
+    atomicAdd(&a.tile_count[tile], 1);
+}
+
+// One workgroup: exclusive scans of node counts and of chunk counts per tile.
+__global__ void __launch_bounds__(1024) k_tile_scan(const int32_t* count, int32_t* offset,
+                                                    int32_t* chunk_off, int64_t ntiles, int cap,
+                                                    unsigned long long* flags) {
+    __shared__ long long s1[1024];
+    __shared__ long long s2[1024];
+    const int tid = threadIdx.x, NT = blockDim.x;
+    int64_t per = (ntiles + NT - 1) / NT;
+    int64_t beg = tid * per, end = beg + per < ntiles ? beg + per : ntiles;
+    long long a = 0, b = 0;
+    for (int64_t i = beg; i < end; ++i) {
+        a += count[i];
+        b += (count[i] + cap - 1) / cap;
+    }
+    s1[tid] = a;
+    s2[tid] = b;
+    __syncthreads();
+    for (int off = 1; off < NT; off *= 2) {
+        long long va = tid >= off ? s1[tid - off] : 0;
+        long long vb = tid >= off ? s2[tid - off] : 0;
+        __syncthreads();
+        s1[tid] += va;
+        s2[tid] += vb;
+        __syncthreads();
+    }
+    long long ea = s1[tid] - a, eb = s2[tid] - b;
+    for (int64_t i = beg; i < end; ++i) {
+        offset[i] = int32_t(ea);
+        chunk_off[i] = int32_t(eb);
+        ea += count[i];
+        eb += (count[i] + cap - 1) / cap;
+    }
+    if (tid == NT - 1) flags[2] = (unsigned long long)s2[NT - 1];
+}
+
+template <typename R, int D>
+__global__ void k_bin_scatter(const R* __restrict__ x, int64_t N, const int32_t* node_tile,
+                              const int32_t* offset, int32_t* cursor, int32_t* perm,
+                              R* __restrict__ xs) {
+    int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    int tile = node_tile[j];
+    int pos = offset[tile] + atomicAdd(&cursor[tile], 1);
+    perm[pos] = int32_t(j);
+#pragma unroll
+    for (int t = 0; t < D; ++t) xs[int64_t(pos) * D + t] = x[j * D + t];
+}
+
+__global__ void k_chunk_fill(const int32_t* count, const int32_t* offset,
+                             const int32_t* chunk_off, int64_t ntiles, int cap, int4* chunks) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int c = count[t];
+    int base = chunk_off[t];
+    for (int s = 0, k = 0; s < c; s += cap, ++k) {
+        int cnt = (c - s) < cap ? (c - s) : cap;
+        chunks[base + k] = make_int4(int(t), offset[t] + s, cnt, 0);
+    }
+}
+
+// ---------------------------------------------------------------- short sums
+struct GatherArgs {
+    const void* theta;     // L^d complex, centred
+    const void* xs;        // sorted nodes
+    const int32_t* perm;
+    const int4* chunks;
+    void* f;
+    int L;
+    int tile[3];
+    int tpd[3];
+    double beta, cb;
+};
+
+template <typename R, int D, int M2, int ACC, int METHOD>
+__global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
+    extern __shared__ unsigned char smem_raw[];
+    Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
+    constexpr int m = M2 / 2;
+    const int4 ch = a.chunks[blockIdx.x];
+    const int L = a.L;
+    // tile origin (cell index in [0, L)) and LDS extents
+    int n0[3] = {0, 0, 0}, W[3] = {1, 1, 1};
+    {
+        int tt = ch.x;
+#pragma unroll
+        for (int t = D - 1; t >= 0; --t) {
+            int tc = tt % a.tpd[t];
+            tt /= a.tpd[t];
+            n0[t] = tc * a.tile[t];
+            W[t] = a.tile[t] + M2 - 1;
+        }
+    }
+    const int total = W[0] * W[1] * W[2];
+    const Cx<R>* __restrict__ th = static_cast<const Cx<R>*>(a.theta);
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        int rem = e;
+        int64_t gidx = 0;
+        bool ok = true;
+#pragma unroll
+        for (int t = D - 1; t >= 0; --t) {
+            int ct = rem % W[t];
+            rem /= W[t];
+            int p = n0[t] - m + 1 + ct;   // cell index of this grid point
+            if (METHOD == 1) {
+                p = (p % L + L) % L;
+            } else if (p < 0 || p >= L) {
+                ok = false;
+            }
+            int64_t st = 1;
+            for (int s = t + 1; s < D; ++s) st *= L;
+            gidx += int64_t(p) * st;
+        }
+        lds[e] = ok ? th[gidx] : Cx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+
+    const R* __restrict__ xs = static_cast<const R*>(a.xs);
+    Cx<R>* __restrict__ f = static_cast<Cx<R>*>(a.f);
+    const R beta = R(a.beta), cb = R(a.cb), inv_m2 = R(1) / R(m * m);
+    for (int jj = threadIdx.x; jj < ch.z; jj += blockDim.x) {
+        const int64_t j = int64_t(ch.y) + jj;
+        R w[D][M2];
+        int r[3] = {0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            int n;
+            R theta;
+            cell_of<R>(xs[j * D + t], L, n, theta);
+            r[t] = n + L / 2 - n0[t];
+            weights<R, M2, METHOD>(theta, beta, cb, inv_m2, w[t]);
+        }
+        Cx<R> res;
+        if constexpr (D == 1) {
+            typename std::conditional<ACC == 1, TwoSumAcc<R>, Plain<R>>::type acc;
+#pragma unroll
+            for (int o = 0; o < M2; ++o) acc.add(w[0][o], lds[r[0] + o]);
+            res = acc.value();
+        } else if constexpr (D == 2) {
+            const int base = r[0] * W[1] + r[1];
+            if constexpr (ACC == 1) {
+                TwoSumAcc<R> acc;
+#pragma unroll
+                for (int o0 = 0; o0 < M2; ++o0) {
+                    const Cx<R>* row = lds + base + o0 * W[1];
+#pragma unroll
+                    for (int o1 = 0; o1 < M2; ++o1) {
+                        const R wp = w[0][o0] * w[1][o1];
+                        acc.add2(wp, dev_fma(w[0][o0], w[1][o1], -wp), row[o1]);
+                    }
+                }
+                res = acc.value();
+            } else {
+                Plain<R> acc;
+#pragma unroll
+                for (int o0 = 0; o0 < M2; ++o0) {
+                    const Cx<R>* row = lds + base + o0 * W[1];
+                    Plain<R> racc;
+#pragma unroll
+                    for (int o1 = 0; o1 < M2; ++o1) racc.add(w[1][o1], row[o1]);
+                    acc.add(w[0][o0], racc.value());
+                }
+                res = acc.value();
+            }
+        } else {
+            const int base = (r[0] * W[1] + r[1]) * W[2] + r[2];
+            if constexpr (ACC == 1) {
+                TwoSumAcc<R> acc;
+#pragma unroll 1
+                for (int o0 = 0; o0 < M2; ++o0) {
+#pragma unroll
+                    for (int o1 = 0; o1 < M2; ++o1) {
+                        const Cx<R>* row = lds + base + (o0 * W[1] + o1) * W[2];
+                        const R w01 = w[0][o0] * w[1][o1];
+                        const R w01l = dev_fma(w[0][o0], w[1][o1], -w01);
+#pragma unroll
+                        for (int o2 = 0; o2 < M2; ++o2) {
+                            const R wp = w01 * w[2][o2];
+                            const R wl = dev_fma(w01, w[2][o2], -wp) + w01l * w[2][o2];
+                            acc.add2(wp, wl, row[o2]);
+                        }
+                    }
+                }
+                res = acc.value();
+            } else {
+                Plain<R> acc;
+#pragma unroll 1
+                for (int o0 = 0; o0 < M2; ++o0) {
+                    Plain<R> pacc;
+#pragma unroll
+                    for (int o1 = 0; o1 < M2; ++o1) {
+                        const Cx<R>* row = lds + base + (o0 * W[1] + o1) * W[2];
+                        Plain<R> racc;
+#pragma unroll
+                        for (int o2 = 0; o2 < M2; ++o2) racc.add(w[2][o2], row[o2]);
+                        pacc.add(w[1][o1], racc.value());
+                    }
+                    acc.add(w[0][o0], pacc.value());
+                }
+                res = acc.value();
+            }
+        }
+        f[a.perm[j]] = res;
+    }
+}
+
+using GatherFn = void (*)(GatherArgs);
+
+template <typename R, int D, int ACC, int METHOD>
+GatherFn pick_m(int m) {
+    switch (m) {
+        case 2: return k_gather<R, D, 4, ACC, METHOD>;
+        case 3: return k_gather<R, D, 6, ACC, METHOD>;
+        case 4: return k_gather<R, D, 8, ACC, METHOD>;
+        case 5: return k_gather<R, D, 10, ACC, METHOD>;
+        case 6: return k_gather<R, D, 12, ACC, METHOD>;
+        case 7: return k_gather<R, D, 14, ACC, METHOD>;
+        case 8: return k_gather<R, D, 16, ACC, METHOD>;
+        default: return nullptr;
+    }
+}
+
+template <typename R, int ACC, int METHOD>
+GatherFn pick_d(int d, int m) {
+    switch (d) {
+        case 1: return pick_m<R, 1, ACC, METHOD>(m);
+        case 2: return pick_m<R, 2, ACC, METHOD>(m);
+        case 3: return pick_m<R, 3, ACC, METHOD>(m);
+        default: return nullptr;
+    }
+}
+
+GatherFn pick_gather(const Plan& p) {
+    const int M = p.method == BL_NFFT ? 1 : 0;
+    if (p.prec == BL_F64)
+        return M ? pick_d<double, 0, 1>(p.d, p.m) : pick_d<double, 0, 0>(p.d, p.m);
+    if (p.prec == BL_F32)
+        return M ? pick_d<float, 0, 1>(p.d, p.m) : pick_d<float, 0, 0>(p.d, p.m);
+    return M ? pick_d<float, 1, 1>(p.d, p.m) : pick_d<float, 1, 0>(p.d, p.m);
+}
+
+}  // namespace
+
+size_t gather_lds_bytes(const Plan& p) {
+    size_t e = 1;
+    for (int t = 0; t < p.d; ++t) e *= size_t(p.tile[t] + 2 * p.m - 1);
+    return e * p.cplx_size();
+}
+
+bl_status launch_binning(Plan& p, const void* x, int64_t N) {
+    BL_HIP(hipMemsetAsync(p.d_tile_count, 0, sizeof(int32_t) * p.ntiles, p.stream));
+    BL_HIP(hipMemsetAsync(p.d_tile_cursor, 0, sizeof(int32_t) * p.ntiles, p.stream));
+    BL_HIP(hipMemsetAsync(p.d_flags, 0, sizeof(unsigned long long) * 4, p.stream));
+    BinArgs a{};
+    a.x = x;
+    a.N = N;
+    a.d = p.d;
+    a.L = int(p.L);
+    a.m = p.m;
+    for (int t = 0; t < 3; ++t) {
+        a.tile[t] = p.tile[t];
+        a.tpd[t] = p.tiles_per_dim[t];
+    }
+    a.node_tile = p.d_node_tile;
+    a.tile_count = p.d_tile_count;
+    a.flags = p.d_flags;
+    const unsigned nb = unsigned((N + 255) / 256);
+    const bool dbl = p.prec == BL_F64;
+    if (N > 0) {
+        if (dbl) {
+            if (p.d == 1) hipLaunchKernelGGL((k_bin_count<double, 1>), dim3(nb), dim3(256), 0, p.stream, a);
+            if (p.d == 2) hipLaunchKernelGGL((k_bin_count<double, 2>), dim3(nb), dim3(256), 0, p.stream, a);
+            if (p.d == 3) hipLaunchKernelGGL((k_bin_count<double, 3>), dim3(nb), dim3(256), 0, p.stream, a);
+        } else {
+            if (p.d == 1) hipLaunchKernelGGL((k_bin_count<float, 1>), dim3(nb), dim3(256), 0, p.stream, a);
+            if (p.d == 2) hipLaunchKernelGGL((k_bin_count<float, 2>), dim3(nb), dim3(256), 0, p.stream, a);
+            if (p.d == 3) hipLaunchKernelGGL((k_bin_count<float, 3>), dim3(nb), dim3(256), 0, p.stream, a);
+        }
+        BL_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, p.stream, p.d_tile_count,
+                       p.d_tile_offset, p.d_chunk_offset, p.ntiles, p.chunk_cap, p.d_flags);
+    BL_HIP(hipGetLastError());
+    if (N > 0) {
+        if (dbl) {
+            const double* xd = static_cast<const double*>(x);
+            double* xs = static_cast<double*>(p.d_xs);
+            if (p.d == 1) hipLaunchKernelGGL((k_bin_scatter<double, 1>), dim3(nb), dim3(256), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
+            if (p.d == 2) hipLaunchKernelGGL((k_bin_scatter<double, 2>), dim3(nb), dim3(256), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
+            if (p.d == 3) hipLaunchKernelGGL((k_bin_scatter<double, 3>), dim3(nb), dim3(256), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
+        } else {
+            const float* xf = static_cast<const float*>(x);
+            float* xs = static_cast<float*>(p.d_xs);
+            if (p.d == 1) hipLaunchKernelGGL((k_bin_scatter<float, 1>), dim3(nb), dim3(256), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
+            if (p.d == 2) hipLaunchKernelGGL((k_bin_scatter<float, 2>), dim3(nb), dim3(256), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
+            if (p.d == 3) hipLaunchKernelGGL((k_bin_scatter<float, 3>), dim3(nb), dim3(256), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
+        }
+        BL_HIP(hipGetLastError());
+    }
+    const unsigned tb = unsigned((p.ntiles + 255) / 256);
+    hipLaunchKernelGGL(k_chunk_fill, dim3(tb), dim3(256), 0, p.stream, p.d_tile_count,
+                       p.d_tile_offset, p.d_chunk_offset, p.ntiles, p.chunk_cap, p.d_chunks);
+    BL_HIP(hipGetLastError());
+    unsigned long long h[4] = {0, 0, 0, 0};
+    BL_HIP(hipMemcpyAsync(h, p.d_flags, sizeof(h), hipMemcpyDeviceToHost, p.stream));
+    BL_HIP(hipStreamSynchronize(p.stream));
+    if (h[0] != 0) {
+        set_error(std::to_string(h[0]) + " node coordinate(s) are NaN/Inf or outside [-1/2, 1/2)");
+        return BL_EDOMAIN;
+    }
+    p.n_outside = int64_t(h[1]);
+    p.nchunks = int64_t(h[2]);
+    if (p.nchunks > p.chunk_alloc) {
+        set_error("internal: chunk count exceeds its bound");
+        return BL_EDEVICE;
+    }
+    return BL_OK;
+}
+
+bl_status launch_gather(Plan& p, const void* theta, void* f) {
+    if (p.N == 0 || p.nchunks == 0) return BL_OK;
+    GatherFn fn = pick_gather(p);
+    if (!fn) {
+        set_error("no short-sum kernel for this (d, m)");
+        return BL_EUNSUPPORTED;
+    }
+    GatherArgs a{};
+    a.theta = theta;
+    a.xs = p.d_xs;
+    a.perm = p.d_perm;
+    a.chunks = p.d_chunks;
+    a.f = f;
+    a.L = int(p.L);
+    for (int t = 0; t < 3; ++t) {
+        a.tile[t] = p.tile[t];
+        a.tpd[t] = p.tiles_per_dim[t];
+    }
+    a.beta = p.beta;
+    a.cb = 1.0 / (-std::expm1(-2.0 * p.beta));
+    const size_t lds = gather_lds_bytes(p);
+    if (lds > 64 * 1024)
+        BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);
+    BL_HIP(hipGetLastError());
+    return BL_OK;
+}
+
+}  // namespace bl

@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded
+inputs.  Tolerances (normwise max error / max |reference|): 1e-12 in FP64, 1e-5 in FP32,
+1e-6 in FP32 with compensated short sums; FP32 runs feed both sides the same
+float32-rounded inputs."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f32c": 1e-6}
+THETA_TOL = {"f64": 1e-13, "f32": 1e-6, "f32c": 1e-7}
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def dev_real(a, prec):
+    torch = torch_mod()
+    return torch.from_numpy(np.ascontiguousarray(a)).to(
+        torch.float64 if prec == "f64" else torch.float32).cuda()
+
+
+def dev_cplx(a, prec):
+    torch = torch_mod()
+    return torch.from_numpy(np.ascontiguousarray(a)).to(
+        torch.complex128 if prec == "f64" else torch.complex64).cuda()
+
+
+def host(t):
+    return t.cpu().numpy().astype(np.complex128 if t.is_complex() else np.float64)
+
+
+def make_plan(p, prec, method="shannon", beta=0.0):
+    from paper_2502_07155_amd import Plan
+    return Plan(p.d, p.M, p.L, p.m, precision=prec, method=method, beta=beta)
+
+
+def oracle_forward(p, method, beta=None):
+    if method == "shannon":
+        return O.forward_shannon(p.fhat, p.x, p.L, p.m, beta, return_stages=True)
+    return O.forward_nfft(p.fhat, p.x, p.L, p.m, beta, return_stages=True)
+
+
+SMALL = [
+    (1, 256, 512, 6, 1000),
+    (1, 64, 128, 2, 777),
+    (1, 40, 64, 8, 500),
+    (2, 64, 128, 5, 5000),
+    (2, 32, 64, 3, 3001),
+    (2, 48, 64, 8, 2000),
+    (3, 16, 32, 4, 3000),
+    (3, 24, 32, 2, 1500),
+]
+
+
+# The classical NFFT with its standard beta = 2 pi m (1 - M/(2L)) is checked at
+# oversampling L = 2M.  At L/M = 4/3 and m = 8 its deconvolution factors 1/phihat span
+# ~1e5 and its short sums cancel ~500-fold, so FP64 parity is limited by the window
+# transform's quadrature (~1e-12) and FP32 loses three digits: a property of that
+# comparison configuration, not of the kernels.
+SMALL_NFFT = [c for c in SMALL if c[2] == 2 * c[1]] + [(1, 32, 64, 8, 500), (2, 32, 64, 8, 2000)]
+CASES = [(c, "shannon") for c in SMALL] + [(c, "nfft") for c in SMALL_NFFT]
+
+
+@pytest.mark.parametrize("case,method", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32c"])
+def test_forward_matches_oracle(case, method, prec):
+    d, M, L, m, N = case
+    p = W.custom_problem(d, M, L, m, N, seed=1000 + 7 * d + M + m,
+                         precision="f32" if prec != "f64" else "f64")
+    plan = make_plan(p, prec, method)
+    plan.set_nodes(dev_real(p.x, prec))
+    f = host(plan.forward(dev_cplx(p.fhat, prec)))
+    theta = host(plan.theta())
+    fo, _, tho = oracle_forward(p, method)
+    print(f"case d={d} M={M} L={L} m={m} N={N} {prec} {method}: "
+          f"theta {O.rel_err_inf(theta, tho):.2e} f {O.rel_err_inf(f, fo):.2e}")
+    assert O.rel_err_inf(theta, tho) <= THETA_TOL[prec]
+    assert O.rel_err_inf(f, fo) <= TOL[prec]
+
+
+@pytest.mark.parametrize("d,M,L,m,N", [(1, 64, 128, 5, 2000), (2, 64, 128, 5, 4000),
+                                       (3, 16, 32, 3, 2000)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32c"])
+def test_interpolate_on_given_samples(d, M, L, m, N, prec):
+    """Step 3 alone: the regularized Shannon sums on samples the oracle provides."""
+    p = W.custom_problem(d, M, L, m, N, seed=77 + d, precision="f32" if prec != "f64" else "f64")
+    rng = W.rng_for(99)
+    theta = W.complex_normal(rng, (L,) * d)
+    if prec != "f64":
+        theta = theta.astype(np.complex64).astype(np.complex128)
+    plan = make_plan(p, prec)
+    plan.set_nodes(dev_real(p.x, prec))
+    f = host(plan.interpolate(dev_cplx(theta, prec)))
+    fo = O.gather_shannon(theta, p.x, L, m, O.default_beta(M, L, m))
+    assert O.rel_err_inf(f, fo) <= TOL[prec]
+
+
+FULL = [
+    ("d1_M256_L512_m6_N1k", "f64"),
+    ("d1_M256_L512_m6_N1k", "f32c"),
+    ("d2_M512_L1024_m5_N1M", "f64"),
+    ("d2_M512_L1024_m5_N1M", "f32"),
+    ("d2_M512_L1024_m5_N1M", "f32c"),
+    ("d3_M128_L256_m4_N2M", "f64"),
+    ("d3_M128_L256_m4_N2M", "f32c"),
+    ("d2_M256_L512_m6_N200k", "f32"),
+]
+
+
+@pytest.mark.parametrize("name,prec", FULL)
+def test_full_size_sampled(name, prec):
+    """Full workload sizes in the benchmark's launch configuration: the whole grid of
+    samples theta is compared, and f on a seeded sample of nodes (oracle short sums)."""
+    p = W.make_problem(name, precision="f32" if prec != "f64" else "f64")
+    plan = make_plan(p, prec)
+    plan.set_nodes(dev_real(p.x, prec))
+    f = host(plan.forward(dev_cplx(p.fhat, prec)))
+    theta = host(plan.theta())
+    beta = O.default_beta(p.M, p.L, p.m)
+    tho = O.inverse_fft_step(O.deconvolve_pad(p.fhat, p.L, p.m, beta))
+    e_theta = O.rel_err_inf(theta, tho)
+    idx = np.sort(W.rng_for(5).choice(p.N, size=min(p.N, 6000), replace=False))
+    fo = O.gather_shannon(tho, p.x[idx], p.L, p.m, beta)
+    e_f = O.rel_err_inf(f[idx], fo)
+    print(f"case {name} {prec}: theta {e_theta:.2e} f(sampled) {e_f:.2e}")
+    assert e_theta <= THETA_TOL[prec]
+    assert e_f <= TOL[prec]
+    st = plan.stats()
+    assert st["n_nodes"] == p.N
+    assert st["n_outside"] == int(np.sum(~O.in_truncated_domain(p.x, p.L, p.m)))
+
+
+def test_edge_nodes_grid_points_and_bounds():
+    """Nodes on grid points (L x integer), at -1/2 exactly, just below 1/2, and clustered
+    into one tile far beyond one work chunk."""
+    from paper_2502_07155_amd import BLNFFTError
+    for prec in ("f64", "f32", "f32c"):
+        d, M, L, m = 2, 32, 64, 4
+        rng = W.rng_for(3)
+        below = float(np.nextafter(np.float32(0.5), np.float32(0))) if prec != "f64" \
+            else float(np.nextafter(0.5, 0.0))
+        ells = rng.integers(-L // 2, L // 2, size=(300, d)) / L
+        special = np.array([[-0.5, -0.5], [-0.5, below], [below, below], [0.0, 0.0],
+                            [below, -0.5], [1.0 / L, -1.0 / L]])
+        cluster = 0.1 + 1e-3 * rng.random((5000, d))
+        x = np.concatenate([ells, special, cluster])
+        if prec != "f64":
+            x = x.astype(np.float32).astype(np.float64)
+        fhat = W.complex_normal(rng, (M,) * d)
+        if prec != "f64":
+            fhat = fhat.astype(np.complex64).astype(np.complex128)
+        p = W.Problem("edge", d, M, L, m, x, fhat)
+        plan = make_plan(p, prec)
+        plan.set_nodes(dev_real(x, prec))
+        assert plan.stats()["n_chunks"] >= 5
+        f = host(plan.forward(dev_cplx(fhat, prec)))
+        fo, _, tho = oracle_forward(p, "shannon")
+        assert O.rel_err_inf(f, fo) <= TOL[prec]
+        # interpolation property on grid points: f = theta there
+        g = np.rint(ells * L).astype(int) + L // 2
+        assert np.max(np.abs(f[:300] - tho[g[:, 0], g[:, 1]])) <= TOL[prec] * np.max(np.abs(tho))
+        # invalid nodes are reported, not computed
+        for bad in (0.5, np.nan, -0.75, np.inf):
+            xb = x.copy()
+            xb[7, 1] = bad
+            with pytest.raises(BLNFFTError) as ei:
+                plan.set_nodes(dev_real(xb, prec))
+            assert ei.value.status == 2
+        with pytest.raises(BLNFFTError) as ei:
+            plan.forward(dev_cplx(fhat, prec))
+        assert ei.value.status == 5
+
+
+def test_zero_nodes_and_reuse():
+    torch = torch_mod()
+    p = W.custom_problem(2, 32, 64, 4, 100, seed=5)
+    plan = make_plan(p, "f64")
+    plan.set_nodes(torch.zeros((0, 2), dtype=torch.float64, device="cuda"))
+    out = plan.forward(dev_cplx(p.fhat, "f64"))
+    assert out.shape == (0,)
+    # growing and shrinking node sets on one plan
+    for n in (100, 20000, 7):
+        q = W.custom_problem(2, 32, 64, 4, n, seed=n)
+        plan.set_nodes(dev_real(q.x, "f64"))
+        f = host(plan.forward(dev_cplx(q.fhat, "f64")))
+        assert O.rel_err_inf(f, O.forward_shannon(q.fhat, q.x, 64, 4)) <= 1e-12
+
+
+def test_forward_is_deterministic():
+    p = W.make_problem("d2_M512_L1024_m5_N1M", N=200_000, precision="f32")
+    plan = make_plan(p, "f32c")
+    plan.set_nodes(dev_real(p.x, "f32c"))
+    fh = dev_cplx(p.fhat, "f32c")
+    a = host(plan.forward(fh))
+    b = host(plan.forward(fh))
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("d,M,L,m,N", [(1, 64, 128, 5, 1500), (2, 32, 64, 4, 3000),
+                                       (3, 16, 32, 3, 1500), (2, 32, 64, 6, 2000)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32c"])
+@pytest.mark.parametrize("method", ["shannon", "nfft"])
+def test_adjoint_matches_oracle(d, M, L, m, N, prec, method):
+    p = W.custom_problem(d, M, L, m, N, seed=300 + d + m, precision="f32" if prec != "f64" else "f64",
+                         with_targets=True)
+    plan = make_plan(p, prec, method)
+    plan.set_nodes(dev_real(p.x, prec))
+    a = host(plan.adjoint(dev_cplx(p.y, prec)))
+    if method == "shannon":
+        ao = O.adjoint_shannon(p.y, p.x, M, L, m)
+    else:
+        ao = O.adjoint_nfft(p.y, p.x, M, L, m)
+    assert O.rel_err_inf(a, ao) <= (1e-12 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("d,M,L,m,N", [(1, 64, 128, 5, 1500), (2, 32, 64, 4, 3000),
+                                       (3, 16, 32, 3, 1500), (2, 256, 512, 6, 20000)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_grad_x_matches_oracle(d, M, L, m, N, prec):
+    p = W.custom_problem(d, M, L, m, N, seed=400 + d + m, precision="f32" if prec != "f64" else "f64",
+                         with_targets=True)
+    plan = make_plan(p, prec)
+    plan.set_nodes(dev_real(p.x, prec))
+    f = plan.forward(dev_cplx(p.fhat, prec))
+    G = 2 * (f - dev_cplx(p.y, prec))
+    gx = host(plan.grad_x(G))
+    Gh = host(G)
+    go = O.grad_x_shannon(p.fhat, Gh, p.x, L, m)
+    assert O.rel_err_inf(gx, go) <= (1e-11 if prec == "f64" else 2e-5)
+
+
+def test_full_size_adjoint_differentiation_workload():
+    """d=2, M=256, L=512, m=6, N=200000 in FP32: adjoint and node gradient vs oracle."""
+    p = W.make_problem("d2_M256_L512_m6_N200k", precision="f32", with_targets=True)
+    plan = make_plan(p, "f32")
+    plan.set_nodes(dev_real(p.x, "f32"))
+    a = host(plan.adjoint(dev_cplx(p.y, "f32")))
+    ao = O.adjoint_shannon(p.y, p.x, p.M, p.L, p.m)
+    assert O.rel_err_inf(a, ao) <= 1e-5
+    f = plan.forward(dev_cplx(p.fhat, "f32"))
+    G = 2 * (f - dev_cplx(p.y, "f32"))
+    gx = host(plan.grad_x(G))
+    idx = np.sort(W.rng_for(8).choice(p.N, size=5000, replace=False))
+    beta = O.default_beta(p.M, p.L, p.m)
+    tho = O.inverse_fft_step(O.deconvolve_pad(p.fhat, p.L, p.m, beta))
+    go = O.grad_x_from_theta(tho, host(G)[idx], p.x[idx], p.L, p.m, beta, "sinh")
+    assert O.rel_err_inf(gx[idx], go) <= 2e-5
