@@ -1,5 +1,6 @@
 // C ABI of the blnfft library: validation, plan lifecycle and call dispatch.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -69,8 +70,11 @@ void free_nodes(Plan& p) {
 void free_plan(Plan& p) {
     free_nodes(p);
     hipFree(p.d_deconv);
-    hipFree(p.d_tw64);
-    hipFree(p.d_tw32);
+    for (FftStages* st : {&p.st16, &p.st4}) {
+        hipFree(st->d_tw64);
+        hipFree(st->d_tw32);
+        st->d_tw64 = st->d_tw32 = nullptr;
+    }
     hipFree(p.d_bufA);
     hipFree(p.d_bufB);
     hipFree(p.d_grid);
@@ -92,6 +96,10 @@ void choose_tiles(Plan& p) {
     if (d == 1) T = 512;
     else if (d == 2) T = 16;
     else T = 8;
+    if (const char* e = std::getenv("BL_TILE")) {   // tuning override
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 4096) T = v;
+    }
     auto bytes = [&](int t) {
         size_t e = 1;
         for (int k = 0; k < d; ++k) e *= size_t(t + 2 * p.m - 1);
@@ -166,11 +174,11 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     if (m < kMinM || m > kMaxM)
         return fail(BL_EUNSUPPORTED, "compiled short-sum kernels cover 2 <= m <= 8");
     if (win != BL_WIN_SINH) return fail(BL_EUNSUPPORTED, "GPU kernels implement the sinh-type window");
-    FftFactors fac;
-    if (L > (1 << 30) || !factor_length(int(L), &fac))
-        return fail(BL_EUNSUPPORTED, "per-plan FFT needs L a power of two");
-    // one line of L complex values per LDS pass: <= 1024 threads in FP32, <= 512 in FP64
-    const int64_t Lmax = (prec == BL_F32) ? 16384 : 8192;
+    FftFactors fac16, fac4;
+    if (L > (1 << 30) || !factor_length(int(L), 16, &fac16) || !factor_length(int(L), 4, &fac4))
+        return fail(BL_EUNSUPPORTED, "per-plan FFT needs L a power of two, L >= 16");
+    // one line of L complex values per LDS pass with <= 512 threads of 16 values each
+    const int64_t Lmax = 8192;
     if (L > Lmax) return fail(BL_EUNSUPPORTED, "L above the LDS FFT limit for this precision");
     const int64_t grid = ipow(L, d);
     if (grid > (int64_t(1) << 31)) return fail(BL_EUNSUPPORTED, "grid L^d too large");
@@ -187,7 +195,6 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     p.prec = prec;
     p.beta = (beta > 0.0) ? beta : default_beta(M, L, m, method);
     p.stream = static_cast<hipStream_t>(stream);
-    p.fac = fac;
     auto cleanup = [&](bl_status s) {
         free_plan(p);
         delete h;
@@ -203,10 +210,31 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
             return cleanup(fail(BL_EINVAL, "window transform vanishes on I_M for this beta"));
         fac_h[i] = 1.0 / (double(L) * hv);
     }
-    std::vector<double> tw;
-    twiddles(L, &tw);
-    std::vector<float> tw32(tw.size());
-    for (size_t i = 0; i < tw.size(); ++i) tw32[i] = float(tw[i]);
+    std::vector<double> tw0;
+    twiddles(L, &tw0);
+    std::vector<double> tw[2];
+    std::vector<float> tw32[2];
+    const FftFactors* facs[2] = {&fac16, &fac4};
+    FftStages* sts[2] = {&p.st16, &p.st4};
+    for (int v = 0; v < 2; ++v) {
+        stage_twiddles(*facs[v], tw0, &tw[v], sts[v]->tw_off);
+        if (tw[v].empty()) tw[v].assign(2, 0.0);
+        sts[v]->tw_len = int(tw[v].size() / 2);
+        sts[v]->nmain = 0;
+        sts[v]->rlast = 1;
+        const int E = v == 0 ? 16 : 4;
+        for (int s = 0; s < facs[v]->nstages; ++s) {
+            if (facs[v]->radix[s] == E) ++sts[v]->nmain;
+            else sts[v]->rlast = facs[v]->radix[s];
+        }
+        tw32[v].resize(tw[v].size());
+        for (size_t i = 0; i < tw[v].size(); ++i) tw32[v][i] = float(tw[v][i]);
+    }
+    if (prec != BL_F64) {
+        std::vector<double> pc;
+        p.poly_err = fit_weight_polys(win, method, m, p.beta, kPolyCoef, &pc);
+        p.poly.assign(pc.begin(), pc.end());
+    }
 
     size_t total = 0;
     bl_status s;
@@ -217,8 +245,10 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     if (d >= 2) A = std::max(ipow(M, d - 1) * L, ipow(L, d - 1) * M);
     if (d >= 3) B = std::max(ipow(M, d - 2) * L * L, ipow(L, d - 2) * M * M);
     if ((s = dev_alloc(&p.d_deconv, sizeof(double) * M, &total)) != BL_OK) return cleanup(s);
-    if ((s = dev_alloc(&p.d_tw64, sizeof(double) * 2 * L, &total)) != BL_OK) return cleanup(s);
-    if ((s = dev_alloc(&p.d_tw32, sizeof(float) * 2 * L, &total)) != BL_OK) return cleanup(s);
+    for (int v = 0; v < 2; ++v) {
+        if ((s = dev_alloc(&sts[v]->d_tw64, sizeof(double) * tw[v].size(), &total)) != BL_OK) return cleanup(s);
+        if ((s = dev_alloc(&sts[v]->d_tw32, sizeof(float) * tw[v].size(), &total)) != BL_OK) return cleanup(s);
+    }
     if ((s = dev_alloc(&p.d_grid, size_t(grid) * c, &total)) != BL_OK) return cleanup(s);
     // F32C keeps the FFT pass intermediates in double.
     const size_t ci = (prec == BL_F32) ? c : 16;
@@ -233,8 +263,11 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     p.workspace_bytes = total;
 
     hipError_t e = hipMemcpyAsync(p.d_deconv, fac_h.data(), sizeof(double) * M, hipMemcpyHostToDevice, p.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p.d_tw64, tw.data(), sizeof(double) * 2 * L, hipMemcpyHostToDevice, p.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(p.d_tw32, tw32.data(), sizeof(float) * 2 * L, hipMemcpyHostToDevice, p.stream);
+    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+        e = hipMemcpyAsync(sts[v]->d_tw64, tw[v].data(), sizeof(double) * tw[v].size(), hipMemcpyHostToDevice, p.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sts[v]->d_tw32, tw32[v].data(), sizeof(float) * tw32[v].size(), hipMemcpyHostToDevice, p.stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
     if (e != hipSuccess) return cleanup(fail(BL_EDEVICE, std::string("table upload: ") + hipGetErrorString(e)));
     *out = h;

@@ -34,6 +34,7 @@ const std::string& last_error();
 constexpr int kMaxStages = 16;
 constexpr int kMinM = 2;    // truncation range of the compiled short-sum kernels
 constexpr int kMaxM = 8;
+constexpr int kPolyCoef = 12;   // coefficients of the float weight polynomials (degree 11)
 
 // Factorisation of one FFT length into Stockham stages.
 struct FftFactors {
@@ -41,7 +42,18 @@ struct FftFactors {
     int nstages = 0;
     int radix[kMaxStages] = {0};
 };
-bool factor_length(int L, FftFactors* out);   // false if L has a prime factor > 7
+// Powers of two L >= 16 as main-radix stages E, ..., E followed by at most one smaller
+// power of two; false otherwise.
+bool factor_length(int L, int E, FftFactors* out);
+
+// Device twiddles of one stage plan: w^{r k} per stage, laid out [k][r-1].
+struct FftStages {
+    int nmain = 0, rlast = 1;
+    int tw_off[kMaxStages] = {0};
+    int tw_len = 0;
+    void* d_tw64 = nullptr;
+    void* d_tw32 = nullptr;
+};
 
 // One pass of the pruned multi-dimensional iFFT: transforms axis `axis` of an array
 // whose axes before `axis` have extent M (still in frequency), `axis` has Min inputs
@@ -65,12 +77,14 @@ struct Plan {
     hipStream_t stream = nullptr;
     int device = 0;
 
-    FftFactors fac;
     // Per-dimension deconvolution factor 1/(L * hat1(k)), k = i - M/2 (FP64, M entries).
     double* d_deconv = nullptr;
-    // Twiddles e^{+2 pi i n / L}, n in [0, L): FP64 and FP32 copies.
-    void* d_tw64 = nullptr;
-    void* d_tw32 = nullptr;
+    // Stage plans with main radix 16 and 4 and their twiddles.
+    FftStages st16, st4;
+    // Float weight polynomials, [m][kPolyCoef] (even then odd coefficients), and the
+    // largest deviation of the fitted weights from the exact ones.
+    std::vector<float> poly;
+    double poly_err = 0.0;
     // Inverse-direction twiddles for the adjoint are the conjugates; computed in kernel.
 
     // FFT ping-pong buffers and the grid of theta (L^d complex).
@@ -125,6 +139,12 @@ double default_beta(int64_t M, int64_t L, int m, bl_method method);
 double window_transform(bl_window win, bl_method method, int64_t L, int m, double beta, double v);
 // e^{2 pi i n / L} for n in [0, L), correctly reduced; interleaved (re, im).
 void twiddles(int64_t L, std::vector<double>* out);
+bool factor_length(int L, int E, FftFactors* out);
+void stage_twiddles(const FftFactors& fac, const std::vector<double>& tw, std::vector<double>* out,
+                    int* off);
+double window_value(bl_window win, bl_method method, int m, double beta, double u);
+double fit_weight_polys(bl_window win, bl_method method, int m, double beta, int nc,
+                        std::vector<double>* coef);
 
 // ---- kernel launchers (fft.hip, gather.hip, bin.hip)
 // Steps 1-2: deconvolve + zero-pad + iFFT, f̂ (M^d) -> grid (L^d).  `sign` = +1 forward

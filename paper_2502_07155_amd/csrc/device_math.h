@@ -11,7 +11,7 @@ namespace bl {
 namespace dev {
 
 template <typename R>
-struct Cx {
+struct alignas(2 * sizeof(R)) Cx {
     R re, im;
 };
 
@@ -133,6 +133,110 @@ __device__ __forceinline__ void weights_and_derivs(R theta, R beta, R cb, R inv_
         }
         w[o] = sc * ph;
         dw[o] = dsc * ph + sc * dph;
+    }
+}
+
+// FP32 weights on the hardware transcendentals (v_sqrt_f32, v_exp_f32 = 2^x, v_rcp_f32):
+//   phi = e^{beta (s - 1)} (1 - e^{-2 beta s}) / (1 - e^{-2 beta}),  s = sqrt(1 - (u/m)^2),
+// with beta (s - 1) = -beta q^2 / (1 + s), q = u/m.  This form matters in float: the
+// window's sensitivity to a rounding of s is beta s ds/s in e^{beta s}, but only
+// beta q^2/(1+s)^2 ds in e^{-beta q^2/(1+s)}, which is small where the weights are large.
+// For the regularized sinc, psi = (-1)^k sin(pi theta)/(pi u) phi with k = m - 1 - o, and
+// one reciprocal 1/((1 + s) u) yields both 1/(1 + s) and 1/u.
+struct WinF32 {
+    float b2;         // beta * log2(e)
+    float cb;         // 1 / (1 - e^{-2 beta})
+    float inv_m2;     // 1 / m^2
+};
+
+// One float weight at offset o, from the exact formula (used for the two edge offsets,
+// where the (m - |u|)^{1/2} behaviour of the window defeats polynomials).  sc is
+// sin(pi theta)/pi/(1 - e^{-2 beta}) for the regularized sinc.
+template <int M2, int METHOD>
+__device__ __forceinline__ float weight_f32_exact(float theta, int o, float sc, const WinF32& wp) {
+    constexpr int m = M2 / 2;
+    const float u = theta + float(m - 1 - o);
+    const float a = float(o + 1) - theta;          // m - u
+    const float b = theta + float(2 * m - 1 - o);  // m + u
+    const float omq = a * b * wp.inv_m2;           // 1 - (u/m)^2 >= 0
+    const float s = __builtin_amdgcn_sqrtf(omq);
+    const float q2 = u * u * wp.inv_m2;
+    const float e2 = __builtin_amdgcn_exp2f(-2.0f * wp.b2 * s);
+    if (METHOD == 0) {
+        const float onep = 1.0f + s;
+        const float rden = __builtin_amdgcn_rcpf(onep * u);
+        const float e1 = __builtin_amdgcn_exp2f(-wp.b2 * q2 * (u * rden));
+        const float sg = ((m - 1 - o) & 1) ? -sc : sc;
+        const float v = sg * e1 * (1.0f - e2) * (onep * rden);
+        return (u == 0.0f) ? 1.0f : v;
+    }
+    const float e1 = __builtin_amdgcn_exp2f(-wp.b2 * q2 * __builtin_amdgcn_rcpf(1.0f + s));
+    return e1 * (1.0f - e2) * wp.cb;
+}
+
+template <int M2, int METHOD>
+__device__ __forceinline__ float edge_scale(float theta, const WinF32& wp) {
+    if (METHOD != 0) return 0.0f;
+    constexpr float kInvPi = 0.31830988618379067154f;
+    const float r = theta < 0.5f ? theta : 1.0f - theta;
+    return sinpif(r) * kInvPi * wp.cb;
+}
+
+template <int M2, int METHOD>
+__device__ __forceinline__ void weights_f32(float theta, const WinF32& wp, float* w) {
+    const float sc = edge_scale<M2, METHOD>(theta, wp);
+#pragma unroll
+    for (int o = 0; o < M2; ++o) w[o] = weight_f32_exact<M2, METHOD>(theta, o, sc, wp);
+}
+
+// Float weights of D coordinates from polynomials (coefficients fitted on the host in
+// double).  psi is even, so offset 2m-1-o at theta equals offset o at 1 - theta, i.e. at
+// -t with t = theta - 1/2: one polynomial P_o(t) = E_o(t^2) + t O_o(t^2) gives both,
+// w[o] = E + t O and w[2m-1-o] = E - t O.  At the edge offsets the window has a square
+// root factor, psi(theta + m - 1) = sqrt(1 - theta) K(theta) with K analytic, so P_0
+// fits K and w[0] = sqrt(1 - theta) P_0(t), w[2m-1] = sqrt(theta) P_0(-t).  coef points
+// to LDS: per o, NC/2 even then NC/2 odd coefficients.
+template <int D, int M2, int NC>
+__device__ __forceinline__ void weights_poly(const float* theta, const float* coef,
+                                             float (*w)[M2]) {
+    constexpr int m = M2 / 2;
+    constexpr int NE = NC / 2;
+    static_assert(NC % 8 == 4 || NC % 8 == 0, "coefficients are read as float4");
+    float t[D], t2[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        t[d] = theta[d] - 0.5f;
+        t2[d] = t[d] * t[d];
+    }
+#pragma unroll
+    for (int o = 0; o < m; ++o) {
+        float c[NC];
+#pragma unroll
+        for (int q = 0; q < NC / 4; ++q) {
+            const float4 v = reinterpret_cast<const float4*>(coef + o * NC)[q];
+            c[4 * q] = v.x;
+            c[4 * q + 1] = v.y;
+            c[4 * q + 2] = v.z;
+            c[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            float E = c[NE - 1], Od = c[NC - 1];
+#pragma unroll
+            for (int k = NE - 2; k >= 0; --k) {
+                E = fmaf(E, t2[d], c[k]);
+                Od = fmaf(Od, t2[d], c[NE + k]);
+            }
+            const float tO = t[d] * Od;
+            const float p = E + tO, q = E - tO;
+            if (o == 0) {
+                w[d][0] = __builtin_amdgcn_sqrtf(1.0f - theta[d]) * p;
+                w[d][M2 - 1] = __builtin_amdgcn_sqrtf(theta[d]) * q;
+            } else {
+                w[d][o] = p;
+                w[d][M2 - 1 - o] = q;
+            }
+        }
     }
 }
 

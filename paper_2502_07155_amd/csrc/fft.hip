@@ -16,12 +16,13 @@
 //    float, computes in double (LDS and registers; FP64 runs at the FP32 vector rate on
 //    this GPU when packed FP32 is not used), keeps the pass intermediates in double and
 //    rounds once, when the grid of samples (or the output band) is stored as float.
+#include <cstdlib>
+
 #include "blnfft_internal.h"
 
 namespace bl {
 namespace {
 
-constexpr int kE = 16;  // complex values per thread per stage
 
 template <typename R>
 struct Cx {
@@ -149,52 +150,36 @@ struct PassArgs {
     const void* in;
     void* out;
     const double* factor;   // M entries (band side), or nullptr
-    const void* tw;         // L complex twiddles e^{+2 pi i n / L}
-    int64_t outer, inner;
+    const void* tw;         // per-stage twiddles, [k][r-1] per stage (tw_off)
+    int outer, inner;       // lines: outer x inner (L^d < 2^31, so 32-bit offsets suffice)
     int Min, Mout, L, M;
     int lgB;                // log2 of lines per workgroup
-    int nstages;
-    int radix[kMaxStages];
+    int lgL;                // log2 of L
+    int tw_in_lds;          // stage the twiddle table in LDS
+    int tw_len;             // complex entries in the twiddle table
+    int nmain;              // stages of the main radix E (the plan is E, ..., E, rlast)
+    int rlast;              // trailing radix (2, 4 or 8 for E = 16; 2 for E = 4), 1 for none
+    int tw_off[kMaxStages];
 };
 
-// One Stockham stage of radix RAD on B interleaved lines in LDS.
-template <typename R, int DIR, int RAD>
-__device__ __forceinline__ void stage(Cx<R>* lds, Cx<R>* reg, const Cx<R>* __restrict__ tw,
-                                      int L, int lgB, int Ns, int tid, int NT) {
-    constexpr int NB = kE / RAD;
-    const int B = 1 << lgB;
-    const int LR = L / RAD;
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        int g = tid + u * NT;
-        int b = g & (B - 1);
-        int j = g >> lgB;
-#pragma unroll
-        for (int r = 0; r < RAD; ++r) reg[u * RAD + r] = lds[padpos(j + r * LR) * B + b];
+// Butterfly g of a stage -> (line b, butterfly index j within the line).  Contiguous
+// lines map consecutive threads to consecutive j (unit stride along the line, which is
+// unit stride in HBM and in the line-major LDS layout); strided lines map consecutive
+// threads to consecutive lines (unit stride in HBM and in the interleaved LDS layout).
+template <bool CONTIG>
+__device__ __forceinline__ void map_butterfly(int g, int lgB, int lgLR, int& b, int& j) {
+    if (CONTIG) {
+        j = g & ((1 << lgLR) - 1);
+        b = g >> lgLR;
+    } else {
+        b = g & ((1 << lgB) - 1);
+        j = g >> lgB;
     }
-    __syncthreads();
-    const int stride = L / (Ns * RAD);
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        int g = tid + u * NT;
-        int b = g & (B - 1);
-        int j = g >> lgB;
-        int k = j % Ns;
-        Cx<R>* a = reg + u * RAD;
-        if (Ns > 1) {
-#pragma unroll
-            for (int r = 1; r < RAD; ++r) {
-                Cx<R> w = tw[r * k * stride];
-                if (DIR < 0) w.im = -w.im;
-                a[r] = cmul(a[r], w);
-            }
-        }
-        dft<R, DIR, RAD>(a);
-        int base = (j - k) * RAD + k;
-#pragma unroll
-        for (int r = 0; r < RAD; ++r) lds[padpos(base + r * Ns) * B + b] = a[out_slot<RAD>(r)];
-    }
-    __syncthreads();
+}
+
+template <bool CONTIG>
+__device__ __forceinline__ int lds_index(int b, int pos, int lgB, int Lp) {
+    return CONTIG ? b * Lp + padpos(pos) : padpos(pos) * (1 << lgB) + b;
 }
 
 template <typename R>
@@ -202,88 +187,211 @@ __device__ __forceinline__ Cx<R> scale(Cx<R> v, double f) {
     return {R(double(v.re) * f), R(double(v.im) * f)};
 }
 
-// DIR +1: forward transform pass (band in, centred full out).
-// DIR -1: adjoint pass (centred full in, band out).
-template <typename R>
-constexpr int max_threads() { return sizeof(R) == 8 ? 512 : 1024; }
+// Global-memory view of one workgroup's B lines.
+template <typename TI, typename R, typename TO, int DIR, bool CONTIG>
+struct LineIO {
+    const Cx<TI>* __restrict__ in;
+    Cx<TO>* __restrict__ out;
+    const double* __restrict__ factor;
+    int o0, i0, outer, inner;
+    int Min, Mout, L, M;
 
-// TI: input element type, R: LDS / arithmetic type, TO: output element type.
-template <typename TI, typename R, typename TO, int DIR>
+    __device__ __forceinline__ bool line(int b, unsigned& base_in, unsigned& base_out) const {
+        const int o = CONTIG ? o0 + b : o0;
+        const int i = CONTIG ? 0 : i0 + b;
+        base_in = unsigned(o) * unsigned(Min) * unsigned(inner) + unsigned(i);
+        base_out = unsigned(o) * unsigned(Mout) * unsigned(inner) + unsigned(i);
+        return o < outer && i < inner;
+    }
+    // FFT input position pos of line b.  Forward: the band sample k with k - M/2 = pos
+    // (mod L), times its factor; other positions are zero.  Adjoint: the centred sample
+    // (pos + L/2) mod L.
+    __device__ __forceinline__ Cx<R> load(int b, int pos) const {
+        unsigned bi, bo;
+        if (!line(b, bi, bo)) return Cx<R>{R(0), R(0)};
+        int k;
+        if (DIR > 0) {
+            k = pos + M / 2;
+            if (k >= L) k -= L;
+            if (k >= Min) return Cx<R>{R(0), R(0)};
+        } else {
+            k = pos + L / 2;
+            if (k >= L) k -= L;
+        }
+        const Cx<TI> v = in[bi + unsigned(k) * unsigned(inner)];
+        Cx<R> r{R(v.re), R(v.im)};
+        if (DIR > 0 && factor) r = scale(r, factor[k]);
+        return r;
+    }
+    // FFT output position q of line b.  Forward: centred index (q + L/2) mod L.  Adjoint:
+    // the band entry k with k - M/2 = q (mod L), times its factor; other q are dropped.
+    __device__ __forceinline__ void store(int b, int q, Cx<R> v) const {
+        unsigned bi, bo;
+        if (!line(b, bi, bo)) return;
+        int k;
+        if (DIR > 0) {
+            k = q + L / 2;
+            if (k >= L) k -= L;
+        } else {
+            k = q + M / 2;
+            if (k >= L) k -= L;
+            if (k >= Mout) return;
+            if (factor) v = scale(v, factor[k]);
+        }
+        out[bo + unsigned(k) * unsigned(inner)] = Cx<TO>{TO(v.re), TO(v.im)};
+    }
+};
+
+// One Stockham stage of radix RAD over the workgroup's B lines, split in its read half
+// and its compute/write half so a caller can overlap the first stage's HBM reads with
+// other work.  Butterfly j of a line reads positions j + r L/RAD, twiddles by w^{r k},
+// k = j mod Ns, w = e^{dir 2 pi i/(Ns RAD)} (tw holds this stage's w^{r k} at
+// k (RAD-1) + r - 1), and writes positions (j - k) RAD + k + r Ns.
+// SRC/DST: 0 = LDS, 1 = global (the first stage reads HBM, the last writes HBM).
+template <typename R, int E, int RAD, bool CONTIG, int SRC, typename IO>
+__device__ __forceinline__ void stage_read(Cx<R>* reg, const Cx<R>* lds, const IO& io, int lgL,
+                                           int lgB, int Lp, int tid, int NT) {
+    constexpr int NB = E / RAD;
+    constexpr int lgR = RAD == 2 ? 1 : RAD == 4 ? 2 : RAD == 8 ? 3 : 4;
+    const int lgLR = lgL - lgR;
+    const int LR = 1 << lgLR;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        int b, j;
+        map_butterfly<CONTIG>(tid + u * NT, lgB, lgLR, b, j);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) {
+            const int pos = j + r * LR;
+            reg[u * RAD + r] = SRC == 0 ? lds[lds_index<CONTIG>(b, pos, lgB, Lp)] : io.load(b, pos);
+        }
+    }
+}
+
+template <typename R, int E, int DIR, int RAD, bool CONTIG, int DST, typename IO>
+__device__ __forceinline__ void stage_write(Cx<R>* reg, Cx<R>* lds, const Cx<R>* __restrict__ tw,
+                                            const IO& io, int lgL, int lgB, int Lp, int Ns,
+                                            int tid, int NT) {
+    constexpr int NB = E / RAD;
+    constexpr int lgR = RAD == 2 ? 1 : RAD == 4 ? 2 : RAD == 8 ? 3 : 4;
+    const int lgLR = lgL - lgR;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        int b, j;
+        map_butterfly<CONTIG>(tid + u * NT, lgB, lgLR, b, j);
+        const int k = j & (Ns - 1);
+        Cx<R>* a = reg + u * RAD;
+        if (Ns > 1) {
+            const Cx<R>* wk = tw + k * (RAD - 1);
+#pragma unroll
+            for (int r = 1; r < RAD; ++r) {
+                Cx<R> w = wk[r - 1];
+                if (DIR < 0) w.im = -w.im;
+                a[r] = cmul(a[r], w);
+            }
+        }
+        dft<R, DIR, RAD>(a);
+        const int base = (j - k) * RAD + k;
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) {
+            const int pos = base + r * Ns;
+            if (DST == 0) lds[lds_index<CONTIG>(b, pos, lgB, Lp)] = a[out_slot<RAD>(r)];
+            else io.store(b, pos, a[out_slot<RAD>(r)]);
+        }
+    }
+}
+
+// Last stage (LDS -> HBM) of radix RAD.
+template <typename R, int E, int DIR, int RAD, bool CONTIG, typename IO>
+__device__ __forceinline__ void last_stage(Cx<R>* reg, Cx<R>* lds, const Cx<R>* tw, const IO& io,
+                                           int lgL, int lgB, int Lp, int Ns, int tid, int NT) {
+    stage_read<R, E, RAD, CONTIG, 0>(reg, lds, io, lgL, lgB, Lp, tid, NT);
+    stage_write<R, E, DIR, RAD, CONTIG, 1>(reg, lds, tw, io, lgL, lgB, Lp, Ns, tid, NT);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Map the
+// hardware block index to a logical one so that consecutive logical blocks (neighbouring
+// lines, which share cache lines in strided passes) run on the same XCD.
+__device__ __forceinline__ int xcd_block(int p, int n) {
+    constexpr int X = 8;
+    const int x = p % X;
+    const int q = n / X, r = n % X;
+    const int start = x * q + (x < r ? x : r);
+    return start + p / X;
+}
+
+template <typename R>
+constexpr int max_threads() { return 512; }
+
+// TI: input element type, R: LDS / arithmetic type, TO: output element type, E: values per
+// thread (= the main radix: 16, or 4 when the pass has few lines and needs more threads).
+template <typename TI, typename R, typename TO, int DIR, bool CONTIG, int E>
 __global__ void __launch_bounds__(max_threads<R>()) k_fft_pass(PassArgs a) {
-    extern __shared__ unsigned char smem_raw[];
-    Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
-    const Cx<TI>* __restrict__ in = static_cast<const Cx<TI>*>(a.in);
-    Cx<TO>* __restrict__ out = static_cast<Cx<TO>*>(a.out);
-    const Cx<R>* __restrict__ tw = static_cast<const Cx<R>*>(a.tw);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x;
     const int NT = blockDim.x;
     const int B = 1 << a.lgB;
     const int L = a.L;
     const int Lp = padpos(L - 1) + 1;
+    Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
+    const Cx<R>* tw = static_cast<const Cx<R>*>(a.tw);
+    const int blk = xcd_block(int(blockIdx.x), int(gridDim.x));
 
-    // line block -> (o0, i0): contiguous lines (inner == 1) group B consecutive outer
-    // indices; strided lines group B consecutive inner indices.
-    int64_t o0, i0;
-    const bool contiguous = (a.inner == 1);
-    if (contiguous) {
-        o0 = int64_t(blockIdx.x) * B;
-        i0 = 0;
+    LineIO<TI, R, TO, DIR, CONTIG> io;
+    io.in = static_cast<const Cx<TI>*>(a.in);
+    io.out = static_cast<Cx<TO>*>(a.out);
+    io.factor = a.factor;
+    io.outer = a.outer;
+    io.inner = a.inner;
+    io.Min = a.Min;
+    io.Mout = a.Mout;
+    io.L = L;
+    io.M = a.M;
+    if (CONTIG) {
+        io.o0 = blk * B;
+        io.i0 = 0;
     } else {
-        int64_t iblocks = (a.inner + B - 1) / B;
-        o0 = int64_t(blockIdx.x) / iblocks;
-        i0 = (int64_t(blockIdx.x) % iblocks) * B;
+        const int iblocks = (a.inner + B - 1) / B;
+        io.o0 = blk / iblocks;
+        io.i0 = (blk % iblocks) * B;
     }
 
-    for (int e = tid; e < B * Lp; e += NT) lds[e] = Cx<R>{R(0), R(0)};
+    // First stage: radix E, Ns = 1 (no twiddles).  Its HBM reads are issued before the
+    // twiddle table is staged, so the two latencies overlap.
+    Cx<R> reg[E];
+    stage_read<R, E, E, CONTIG, 1>(reg, lds, io, a.lgL, a.lgB, Lp, tid, NT);
+    if (a.tw_in_lds) {
+        Cx<R>* twl = lds + size_t(B) * Lp;
+        for (int e = tid; e < a.tw_len; e += NT) twl[e] = tw[e];
+        tw = twl;
+    }
+    const int nstages = a.nmain + (a.rlast > 1 ? 1 : 0);
+    if (nstages == 1) {
+        stage_write<R, E, DIR, E, CONTIG, 1>(reg, lds, tw, io, a.lgL, a.lgB, Lp, 1, tid, NT);
+        return;
+    }
+    stage_write<R, E, DIR, E, CONTIG, 0>(reg, lds, tw, io, a.lgL, a.lgB, Lp, 1, tid, NT);
     __syncthreads();
-
-    // ---- load
-    const int half_in = (DIR > 0) ? a.M / 2 : L / 2;
-    const int nin = B * a.Min;
-    for (int e = tid; e < nin; e += NT) {
-        int b, k;
-        if (contiguous) { b = e / a.Min; k = e - b * a.Min; }
-        else { b = e & (B - 1); k = e >> a.lgB; }
-        int64_t o = contiguous ? o0 + b : o0;
-        int64_t i = contiguous ? 0 : i0 + b;
-        if (o >= a.outer || i >= a.inner) continue;
-        const Cx<TI> vi = in[(o * a.Min + k) * a.inner + i];
-        Cx<R> v{R(vi.re), R(vi.im)};
-        if (DIR > 0 && a.factor) v = scale(v, a.factor[k]);
-        int pos = k - half_in;
-        pos += (pos < 0) ? L : 0;
-        lds[padpos(pos) * B + b] = v;
+    int Ns = E;
+    // middle radix-E stages, LDS -> LDS in place
+    const int nmid = a.nmain - 1 - (a.rlast > 1 ? 0 : 1);
+    for (int s = 1; s <= nmid; ++s) {
+        stage_read<R, E, E, CONTIG, 0>(reg, lds, io, a.lgL, a.lgB, Lp, tid, NT);
+        __syncthreads();
+        stage_write<R, E, DIR, E, CONTIG, 0>(reg, lds, tw + a.tw_off[s], io, a.lgL, a.lgB, Lp, Ns, tid, NT);
+        __syncthreads();
+        Ns *= E;
     }
-    __syncthreads();
-
-    // ---- Stockham stages
-    Cx<R> reg[kE];
-    int Ns = 1;
-    for (int s = 0; s < a.nstages; ++s) {
-        int rad = a.radix[s];
-        if (rad == 16) stage<R, DIR, 16>(lds, reg, tw, L, a.lgB, Ns, tid, NT);
-        else if (rad == 8) stage<R, DIR, 8>(lds, reg, tw, L, a.lgB, Ns, tid, NT);
-        else if (rad == 4) stage<R, DIR, 4>(lds, reg, tw, L, a.lgB, Ns, tid, NT);
-        else stage<R, DIR, 2>(lds, reg, tw, L, a.lgB, Ns, tid, NT);
-        Ns *= rad;
-    }
-
-    // ---- store
-    const int half_out = (DIR > 0) ? L / 2 : a.M / 2;
-    const int nout = B * a.Mout;
-    for (int e = tid; e < nout; e += NT) {
-        int b, q;
-        if (contiguous) { b = e / a.Mout; q = e - b * a.Mout; }
-        else { b = e & (B - 1); q = e >> a.lgB; }
-        int64_t o = contiguous ? o0 + b : o0;
-        int64_t i = contiguous ? 0 : i0 + b;
-        if (o >= a.outer || i >= a.inner) continue;
-        // output index q holds frequency / grid point q - half_out, FFT position mod L
-        int pos = q - half_out;
-        pos += (pos < 0) ? L : 0;
-        Cx<R> v = lds[padpos(pos) * B + b];
-        if (DIR < 0 && a.factor) v = scale(v, a.factor[q]);
-        out[(o * a.Mout + q) * a.inner + i] = Cx<TO>{TO(v.re), TO(v.im)};
+    const Cx<R>* twl = tw + a.tw_off[nstages - 1];
+    if constexpr (E == 16) {
+        switch (a.rlast) {
+            case 2: last_stage<R, E, DIR, 2, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
+            case 4: last_stage<R, E, DIR, 4, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
+            case 8: last_stage<R, E, DIR, 8, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
+            default: last_stage<R, E, DIR, 16, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
+        }
+    } else {
+        if (a.rlast == 2) last_stage<R, E, DIR, 2, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT);
+        else last_stage<R, E, DIR, E, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT);
     }
 }
 
@@ -295,48 +403,84 @@ int ilog2(int v) {
 
 // Lines per workgroup: enough to coalesce strided accesses, threads B*L/E <= 1024, and
 // LDS within `lds_cap` bytes.
-int choose_lines(const Plan& p, size_t c) {
+// Lines per workgroup: enough to coalesce strided accesses, threads B*L/E <= 512, and
+// LDS within 96 KB.
+int choose_lines(const Plan& p, size_t c, int E) {
     const int L = int(p.L);
     const int bmax = (c == 16) ? 8 : 16;
-    const int tmax = (c == 16) ? 512 : 1024;
+    const int tmax = 512;
     int b = 1;
-    while (b * 2 <= bmax && (int64_t(b) * 2 * L) / kE <= tmax &&
+    while (b * 2 <= bmax && (int64_t(b) * 2 * L) / E <= tmax &&
            size_t(b) * 2 * size_t(padpos(L - 1) + 1) * c <= 96 * 1024)
         b *= 2;
-    // at least E values per... B*L must be a multiple of E and give >= 1 wave
-    while ((int64_t(b) * L) % kE != 0 || (int64_t(b) * L) / kE < 64) {
+    if (const char* e = std::getenv("BL_FFT_LINES")) {   // tuning override
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 64 && (v & (v - 1)) == 0) b = v;
+    }
+    // B*L must be a multiple of E and give at least one wave
+    while ((int64_t(b) * L) % E != 0 || (int64_t(b) * L) / E < 64) {
         if (b >= 1024) break;
         b *= 2;
     }
     return b;
 }
 
-template <typename TI, typename R, typename TO, int DIR>
-bl_status run_pass(Plan& p, const PassArgs& a0) {
-    PassArgs a = a0;
+// Values per thread.  Radix-4 stages (four values per thread) measured faster than
+// radix-16 ones at every size used here: the passes are latency-bound, and four times the
+// threads hide more of it than the fewer LDS round trips of radix 16 save.
+int choose_radix(const Plan& p, int64_t lines) {
+    if (const char* e = std::getenv("BL_FFT_RADIX")) {   // tuning override
+        const int v = std::atoi(e);
+        if (v == 4 || v == 16) return v;
+    }
+    (void)lines;
+    return 4;
+}
+
+template <typename TI, typename R, typename TO, int DIR, int E>
+bl_status run_pass_e(Plan& p, PassArgs a) {
     const bool contiguous = (a.inner == 1);
-    int B = choose_lines(p, sizeof(Cx<R>));
+    const int B = choose_lines(p, sizeof(Cx<R>), E);
     a.lgB = ilog2(B);
+    a.lgL = ilog2(a.L);
     const int L = a.L;
-    const int NT = int((int64_t(B) * L) / kE);
-    const size_t lds = size_t(B) * size_t(padpos(L - 1) + 1) * sizeof(Cx<R>);
+    const int NT = int((int64_t(B) * L) / E);
+    const size_t data = size_t(B) * size_t(padpos(L - 1) + 1) * sizeof(Cx<R>);
+    const size_t twb = size_t(a.tw_len) * sizeof(Cx<R>);
+    a.tw_in_lds = (twb <= 32 * 1024 && data + twb <= 160 * 1024) ? 1 : 0;
+    const size_t lds = data + (a.tw_in_lds ? twb : 0);
     if (NT > max_threads<R>() || lds > 160 * 1024) {
         set_error("FFT length too large for the LDS pass kernel");
         return BL_EUNSUPPORTED;
     }
-    int64_t nblocks = contiguous ? (a.outer + B - 1) / B : a.outer * ((a.inner + B - 1) / B);
+    int64_t nblocks = contiguous ? (int64_t(a.outer) + B - 1) / B
+                                 : int64_t(a.outer) * ((int64_t(a.inner) + B - 1) / B);
     if (nblocks == 0) return BL_OK;
     if (nblocks > 0x7fffffffLL) {
         set_error("FFT pass grid too large");
         return BL_EUNSUPPORTED;
     }
-    auto kern = k_fft_pass<TI, R, TO, DIR>;
+    auto kern = contiguous ? k_fft_pass<TI, R, TO, DIR, true, E> : k_fft_pass<TI, R, TO, DIR, false, E>;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    int(lds)));
     hipLaunchKernelGGL(kern, dim3(unsigned(nblocks)), dim3(NT), lds, p.stream, a);
     BL_HIP(hipGetLastError());
     return BL_OK;
+}
+
+template <typename TI, typename R, typename TO, int DIR>
+bl_status run_pass(Plan& p, PassArgs a) {
+    const int64_t lines = int64_t(a.outer) * a.inner;
+    const int E = choose_radix(p, lines);
+    const FftStages& st = E == 16 ? p.st16 : p.st4;
+    a.nmain = st.nmain;
+    a.rlast = st.rlast;
+    for (int s = 0; s < kMaxStages; ++s) a.tw_off[s] = st.tw_off[s];
+    a.tw = sizeof(R) == 8 ? st.d_tw64 : st.d_tw32;
+    a.tw_len = st.tw_len;
+    if (E == 16) return run_pass_e<TI, R, TO, DIR, 16>(p, a);
+    return run_pass_e<TI, R, TO, DIR, 4>(p, a);
 }
 
 // Element types of one pass.  F64: all double.  F32: all float.  F32C: float input and
@@ -363,13 +507,10 @@ bl_status dispatch_pass(Plan& p, const PassArgs& a, PassTypes t) {
     return run_pass<float, float, float, DIR>(p, a);
 }
 
-void fill_common(const Plan& p, PassArgs& a, bool comp64) {
+void fill_common(const Plan& p, PassArgs& a) {
     a.factor = p.d_deconv;
-    a.tw = comp64 ? p.d_tw64 : p.d_tw32;
     a.L = int(p.L);
     a.M = int(p.M);
-    a.nstages = p.fac.nstages;
-    for (int s = 0; s < p.fac.nstages; ++s) a.radix[s] = p.fac.radix[s];
 }
 
 // Forward: f̂ (M^d) -> grid (L^d).  Axis d-1 first; after the pass over axis a, axes
@@ -383,11 +524,11 @@ bl_status forward_fft(Plan& p, const void* fhat) {
         a.in = src;
         void* dst = (axis == 0) ? p.d_grid : ((axis == d - 1) ? p.d_bufA : p.d_bufB);
         a.out = dst;
-        fill_common(p, a, t.comp64);
+        fill_common(p, a);
         a.outer = 1;
-        for (int k = 0; k < axis; ++k) a.outer *= p.M;
+        for (int k = 0; k < axis; ++k) a.outer *= int(p.M);
         a.inner = 1;
-        for (int k = axis + 1; k < d; ++k) a.inner *= p.L;
+        for (int k = axis + 1; k < d; ++k) a.inner *= int(p.L);
         a.Min = int(p.M);
         a.Mout = int(p.L);
         BL_TRY(dispatch_pass<+1>(p, a, t));
@@ -407,11 +548,11 @@ bl_status adjoint_fft(Plan& p, const void* grid, void* fhat_out) {
         a.in = src;
         void* dst = (axis == 0) ? fhat_out : ((axis == d - 1) ? p.d_bufA : p.d_bufB);
         a.out = dst;
-        fill_common(p, a, t.comp64);
+        fill_common(p, a);
         a.outer = 1;
-        for (int k = 0; k < axis; ++k) a.outer *= p.L;
+        for (int k = 0; k < axis; ++k) a.outer *= int(p.L);
         a.inner = 1;
-        for (int k = axis + 1; k < d; ++k) a.inner *= p.M;
+        for (int k = axis + 1; k < d; ++k) a.inner *= int(p.M);
         a.Min = int(p.L);
         a.Mout = int(p.M);
         BL_TRY(dispatch_pass<-1>(p, a, t));

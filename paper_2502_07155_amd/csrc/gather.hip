@@ -12,6 +12,8 @@
 // J_{L,m}(x) have sinc(+-m pi) phi(+-m/L) = 0.  The offset u = L x - l = theta + m - 1 - o,
 // and sin(pi u) = (-1)^{m-1-o} sin(pi theta), so one sin per node and dimension serves all
 // 2m weights; sin(pi theta) is reduced to [0, 1/2] by reflection.
+#include <cstdlib>
+
 #include "blnfft_internal.h"
 #include "device_math.h"
 
@@ -117,6 +119,94 @@ __global__ void k_chunk_fill(const int32_t* count, const int32_t* offset,
     }
 }
 
+// Within one chunk, order the nodes by their cell inside the tile (row-major), so that
+// neighbouring lanes of the short-sum kernel read neighbouring samples from LDS.  LDS
+// counting sort over the tile's cells; the chunk's sorted nodes and permutation are
+// rewritten in place (all reads complete before the first write).
+constexpr int kSortPerThread = 4;   // chunk_cap / 256
+
+struct SortArgs {
+    const int4* chunks;
+    void* xs;
+    int32_t* perm;
+    int L;
+    int tile[3];
+    int tpd[3];
+};
+
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_chunk_sort(SortArgs a) {
+    extern __shared__ int hist[];
+    __shared__ int part[256];
+    const int4 ch = a.chunks[blockIdx.x];
+    int n0[3] = {0, 0, 0};
+    int tvol = 1;
+    {
+        int tt = ch.x;
+#pragma unroll
+        for (int t = D - 1; t >= 0; --t) {
+            n0[t] = (tt % a.tpd[t]) * a.tile[t];
+            tt /= a.tpd[t];
+            tvol *= a.tile[t];
+        }
+    }
+    for (int e = threadIdx.x; e < tvol; e += blockDim.x) hist[e] = 0;
+    __syncthreads();
+    R* xs = static_cast<R*>(a.xs);
+    R xv[kSortPerThread][D];
+    int pv[kSortPerThread], key[kSortPerThread], rank[kSortPerThread];
+#pragma unroll
+    for (int q = 0; q < kSortPerThread; ++q) {
+        const int jj = threadIdx.x + q * blockDim.x;
+        key[q] = -1;
+        if (jj < ch.z) {
+            const int64_t j = int64_t(ch.y) + jj;
+            int k = 0;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                xv[q][t] = xs[j * D + t];
+                int n;
+                R th;
+                cell_of<R>(xv[q][t], a.L, n, th);
+                k = k * a.tile[t] + (n + a.L / 2 - n0[t]);
+            }
+            pv[q] = a.perm[j];
+            key[q] = k;
+            rank[q] = atomicAdd(&hist[k], 1);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of hist[0..tvol)
+    const int per = (tvol + blockDim.x - 1) / blockDim.x;
+    const int beg = threadIdx.x * per;
+    const int end = beg + per < tvol ? beg + per : tvol;
+    int sum = 0;
+    for (int e = beg; e < end; ++e) sum += hist[e];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < int(blockDim.x); off *= 2) {
+        const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = part[threadIdx.x] - sum;
+    for (int e = beg; e < end; ++e) {
+        const int c = hist[e];
+        hist[e] = run;
+        run += c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSortPerThread; ++q) {
+        if (key[q] < 0) continue;
+        const int64_t pos = int64_t(ch.y) + hist[key[q]] + rank[q];
+#pragma unroll
+        for (int t = 0; t < D; ++t) xs[pos * D + t] = xv[q][t];
+        a.perm[pos] = pv[q];
+    }
+}
+
 // ---------------------------------------------------------------- short sums
 struct GatherArgs {
     const void* theta;     // L^d complex, centred
@@ -127,12 +217,15 @@ struct GatherArgs {
     int L;
     int tile[3];
     int tpd[3];
+    int pitch[3];          // LDS pitch (elements) of each tile dimension
     double beta, cb;
+    WinF32 wf;             // float window constants
+    alignas(16) float poly[kMaxM * kPolyCoef];   // float weight polynomials (see weights_poly)
 };
 
 template <typename R, int D, int M2, int ACC, int METHOD>
 __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
     constexpr int m = M2 / 2;
     const int4 ch = a.chunks[blockIdx.x];
@@ -150,15 +243,28 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
         }
     }
     const int total = W[0] * W[1] * W[2];
+    // LDS strides: dimension t advances by S[t] elements; the innermost row is padded to
+    // a.pitch[D-1] elements.
+    int S[3] = {1, 1, 1};
+    if (D >= 2) S[D - 2] = a.pitch[D - 1];
+    if (D >= 3) S[0] = S[1] * W[1];
+    const int lds_elems = S[0] * W[0];
     const Cx<R>* __restrict__ th = static_cast<const Cx<R>*>(a.theta);
+    // float weight polynomials after the tile in LDS, 16-byte aligned
+    float* coef = reinterpret_cast<float*>(smem_raw + ((size_t(lds_elems) * sizeof(Cx<R>) + 15) & ~size_t(15)));
+    if constexpr (std::is_same<R, float>::value && M2 > 12) {
+        for (int e = threadIdx.x; e < m * kPolyCoef; e += blockDim.x) coef[e] = a.poly[e];
+    }
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
         int rem = e;
         int64_t gidx = 0;
+        int li = 0;
         bool ok = true;
 #pragma unroll
         for (int t = D - 1; t >= 0; --t) {
             int ct = rem % W[t];
             rem /= W[t];
+            li += ct * S[t];
             int p = n0[t] - m + 1 + ct;   // cell index of this grid point
             if (METHOD == 1) {
                 p = (p % L + L) % L;
@@ -169,94 +275,71 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
             for (int s = t + 1; s < D; ++s) st *= L;
             gidx += int64_t(p) * st;
         }
-        lds[e] = ok ? th[gidx] : Cx<R>{R(0), R(0)};
+        lds[li] = ok ? th[gidx] : Cx<R>{R(0), R(0)};
     }
     __syncthreads();
 
     const R* __restrict__ xs = static_cast<const R*>(a.xs);
     Cx<R>* __restrict__ f = static_cast<Cx<R>*>(a.f);
-    const R beta = R(a.beta), cb = R(a.cb), inv_m2 = R(1) / R(m * m);
     for (int jj = threadIdx.x; jj < ch.z; jj += blockDim.x) {
         const int64_t j = int64_t(ch.y) + jj;
         R w[D][M2];
+        R theta[D];
         int r[3] = {0, 0, 0};
 #pragma unroll
         for (int t = 0; t < D; ++t) {
             int n;
-            R theta;
-            cell_of<R>(xs[j * D + t], L, n, theta);
+            cell_of<R>(xs[j * D + t], L, n, theta[t]);
             r[t] = n + L / 2 - n0[t];
-            weights<R, M2, METHOD>(theta, beta, cb, inv_m2, w[t]);
         }
+        if constexpr (std::is_same<R, float>::value) {
+            // m <= 6: coefficients straight from the kernel arguments (SGPRs); larger m
+            // would spill SGPRs, so those read them from LDS (broadcast).
+            if constexpr (M2 <= 12) weights_poly<D, M2, kPolyCoef>(theta, a.poly, w);
+            else weights_poly<D, M2, kPolyCoef>(theta, coef, w);
+        } else {
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                weights<R, M2, METHOD>(theta[t], R(a.beta), R(a.cb), R(1) / R(m * m), w[t]);
+        }
+        // Separable contraction: plain FMA sums along the last dimension(s); with ACC == 1
+        // the outermost sum is compensated (error-free products and two-sum).
+        using Outer = typename std::conditional<ACC == 1, TwoSumAcc<R>, Plain<R>>::type;
         Cx<R> res;
         if constexpr (D == 1) {
-            typename std::conditional<ACC == 1, TwoSumAcc<R>, Plain<R>>::type acc;
+            Outer acc;
 #pragma unroll
             for (int o = 0; o < M2; ++o) acc.add(w[0][o], lds[r[0] + o]);
             res = acc.value();
         } else if constexpr (D == 2) {
-            const int base = r[0] * W[1] + r[1];
-            if constexpr (ACC == 1) {
-                TwoSumAcc<R> acc;
+            const int base = r[0] * S[0] + r[1];
+            Outer acc;
 #pragma unroll
-                for (int o0 = 0; o0 < M2; ++o0) {
-                    const Cx<R>* row = lds + base + o0 * W[1];
+            for (int o0 = 0; o0 < M2; ++o0) {
+                const Cx<R>* row = lds + base + o0 * S[0];
+                Plain<R> racc;
 #pragma unroll
-                    for (int o1 = 0; o1 < M2; ++o1) {
-                        const R wp = w[0][o0] * w[1][o1];
-                        acc.add2(wp, dev_fma(w[0][o0], w[1][o1], -wp), row[o1]);
-                    }
-                }
-                res = acc.value();
-            } else {
-                Plain<R> acc;
+                for (int o1 = 0; o1 < M2; ++o1) racc.add(w[1][o1], row[o1]);
+                acc.add(w[0][o0], racc.value());
+            }
+            res = acc.value();
+        } else {
+            const int base = r[0] * S[0] + r[1] * S[1] + r[2];
+            Outer acc;
+#pragma unroll 1
+            for (int o0 = 0; o0 < M2; ++o0) {
+                Plain<R> pacc;
 #pragma unroll
-                for (int o0 = 0; o0 < M2; ++o0) {
-                    const Cx<R>* row = lds + base + o0 * W[1];
+                for (int o1 = 0; o1 < M2; ++o1) {
+                    const Cx<R>* row = lds + base + o0 * S[0] + o1 * S[1];
                     Plain<R> racc;
 #pragma unroll
-                    for (int o1 = 0; o1 < M2; ++o1) racc.add(w[1][o1], row[o1]);
-                    acc.add(w[0][o0], racc.value());
+                    for (int o2 = 0; o2 < M2; ++o2) racc.add(w[2][o2], row[o2]);
+                    pacc.add(w[1][o1], racc.value());
                 }
-                res = acc.value();
+                acc.add(w[0][o0], pacc.value());
             }
-        } else {
-            const int base = (r[0] * W[1] + r[1]) * W[2] + r[2];
-            if constexpr (ACC == 1) {
-                TwoSumAcc<R> acc;
-#pragma unroll 1
-                for (int o0 = 0; o0 < M2; ++o0) {
-#pragma unroll
-                    for (int o1 = 0; o1 < M2; ++o1) {
-                        const Cx<R>* row = lds + base + (o0 * W[1] + o1) * W[2];
-                        const R w01 = w[0][o0] * w[1][o1];
-                        const R w01l = dev_fma(w[0][o0], w[1][o1], -w01);
-#pragma unroll
-                        for (int o2 = 0; o2 < M2; ++o2) {
-                            const R wp = w01 * w[2][o2];
-                            const R wl = dev_fma(w01, w[2][o2], -wp) + w01l * w[2][o2];
-                            acc.add2(wp, wl, row[o2]);
-                        }
-                    }
-                }
-                res = acc.value();
-            } else {
-                Plain<R> acc;
-#pragma unroll 1
-                for (int o0 = 0; o0 < M2; ++o0) {
-                    Plain<R> pacc;
-#pragma unroll
-                    for (int o1 = 0; o1 < M2; ++o1) {
-                        const Cx<R>* row = lds + base + (o0 * W[1] + o1) * W[2];
-                        Plain<R> racc;
-#pragma unroll
-                        for (int o2 = 0; o2 < M2; ++o2) racc.add(w[2][o2], row[o2]);
-                        pacc.add(w[1][o1], racc.value());
-                    }
-                    acc.add(w[0][o0], pacc.value());
-                }
-                res = acc.value();
-            }
+            res = acc.value();
         }
         f[a.perm[j]] = res;
     }
@@ -299,9 +382,33 @@ GatherFn pick_gather(const Plan& p) {
 
 }  // namespace
 
+dev::WinF32 make_win_f32(const Plan& p) {
+    dev::WinF32 w;
+    w.b2 = float(p.beta * 1.44269504088896340736);   // beta log2(e)
+    w.cb = float(1.0 / (-std::expm1(-2.0 * p.beta)));
+    w.inv_m2 = float(1.0 / (double(p.m) * double(p.m)));
+    return w;
+}
+
+// LDS pitch (elements) of the staged tile's innermost row.  Rows are padded so that a
+// row step moves by half of the 64 LDS banks: lanes reading neighbouring tile rows then
+// fall on disjoint banks.
+int tile_pitch(const Plan& p) {
+    const int w = p.tile[p.d - 1] + 2 * p.m - 1;
+    int mode = 1;
+    if (const char* e = std::getenv("BL_PITCH")) mode = std::atoi(e);   // tuning override
+    if (p.d == 1 || mode == 0) return w;
+    if (mode == 2) return w | 1;
+    if (p.d != 2) return w;   // measured: padding helps d = 2 tiles, not d = 3
+    const int words = int(p.cplx_size() / 4);   // 32-bit banks per element
+    for (int q = w; q < w + 64; ++q)
+        if ((q * words) % 64 == 32) return q;
+    return w;
+}
+
 size_t gather_lds_bytes(const Plan& p) {
-    size_t e = 1;
-    for (int t = 0; t < p.d; ++t) e *= size_t(p.tile[t] + 2 * p.m - 1);
+    size_t e = size_t(tile_pitch(p));
+    for (int t = 0; t + 1 < p.d; ++t) e *= size_t(p.tile[t] + 2 * p.m - 1);
     return e * p.cplx_size();
 }
 
@@ -372,6 +479,36 @@ bl_status launch_binning(Plan& p, const void* x, int64_t N) {
         set_error("internal: chunk count exceeds its bound");
         return BL_EDEVICE;
     }
+    if (p.nchunks > 0) {
+        if (p.chunk_cap > 256 * kSortPerThread) {
+            set_error("internal: chunk capacity above the sort kernel's");
+            return BL_EDEVICE;
+        }
+        SortArgs s{};
+        s.chunks = p.d_chunks;
+        s.xs = p.d_xs;
+        s.perm = p.d_perm;
+        s.L = int(p.L);
+        int tvol = 1;
+        for (int t = 0; t < 3; ++t) {
+            s.tile[t] = p.tile[t];
+            s.tpd[t] = p.tiles_per_dim[t];
+            tvol *= p.tile[t];
+        }
+        const size_t sh = sizeof(int) * size_t(tvol);
+        const dim3 grid(unsigned(p.nchunks)), blk(256);
+        if (dbl) {
+            if (p.d == 1) hipLaunchKernelGGL((k_chunk_sort<double, 1>), grid, blk, sh, p.stream, s);
+            if (p.d == 2) hipLaunchKernelGGL((k_chunk_sort<double, 2>), grid, blk, sh, p.stream, s);
+            if (p.d == 3) hipLaunchKernelGGL((k_chunk_sort<double, 3>), grid, blk, sh, p.stream, s);
+        } else {
+            if (p.d == 1) hipLaunchKernelGGL((k_chunk_sort<float, 1>), grid, blk, sh, p.stream, s);
+            if (p.d == 2) hipLaunchKernelGGL((k_chunk_sort<float, 2>), grid, blk, sh, p.stream, s);
+            if (p.d == 3) hipLaunchKernelGGL((k_chunk_sort<float, 3>), grid, blk, sh, p.stream, s);
+        }
+        BL_HIP(hipGetLastError());
+        BL_HIP(hipStreamSynchronize(p.stream));
+    }
     return BL_OK;
 }
 
@@ -392,10 +529,13 @@ bl_status launch_gather(Plan& p, const void* theta, void* f) {
     for (int t = 0; t < 3; ++t) {
         a.tile[t] = p.tile[t];
         a.tpd[t] = p.tiles_per_dim[t];
+        a.pitch[t] = (t == p.d - 1) ? tile_pitch(p) : (t < p.d ? p.tile[t] + 2 * p.m - 1 : 1);
     }
     a.beta = p.beta;
     a.cb = 1.0 / (-std::expm1(-2.0 * p.beta));
-    const size_t lds = gather_lds_bytes(p);
+    a.wf = make_win_f32(p);
+    for (size_t i = 0; i < p.poly.size() && i < size_t(kMaxM * kPolyCoef); ++i) a.poly[i] = p.poly[i];
+    const size_t lds = gather_lds_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);

@@ -1,5 +1,6 @@
 // Host-side FP64 tables: window transforms (deconvolution factors), default beta,
 // twiddle factors and FFT factorisations.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -112,18 +113,111 @@ void twiddles(int64_t L, std::vector<double>* out) {
     }
 }
 
-// Radices 16, 8, 4, 2 for powers of two (the compiled Stockham stages).
-bool factor_length(int L, FftFactors* out) {
+// Regularized sinc psi_g(u) (shannon) or window phi_g(u) (nfft) in grid units, u = L x - l.
+double window_value(bl_window win, bl_method method, int m, double beta, double u) {
+    const double a = std::fabs(u);
+    if (a >= double(m)) return 0.0;
+    double v = window_g(win, m, beta, a, double(m) - a);
+    if (method == BL_SHANNON) v *= (u == 0.0) ? 1.0 : sin_pi(u) / (kPi * u);
+    return v;
+}
+
+// Polynomials for the float short-sum weights.  Offset o carries u = theta + m - 1 - o,
+// theta in [0, 1].  For o = 1..m-1 the weight itself, for o = 0 the factor
+// K(theta) = w_0(theta) / sqrt(1 - theta) (analytic: the window's square-root behaviour
+// at |u| = m is taken out).  Each is interpolated at nc Chebyshev points of theta in
+// [0, 1], converted to monomials in t = theta - 1/2 and stored as nc/2 even then nc/2
+// odd coefficients (the kernel uses w_{2m-1-o}(theta) = w_o(1 - theta)).  Returns the
+// largest deviation of the resulting weights from the exact ones, all 2m offsets, in
+// double.
+double fit_weight_polys(bl_window win, bl_method method, int m, double beta, int nc,
+                        std::vector<double>* coef) {
+    const int n = nc;
+    coef->assign(size_t(m) * nc, 0.0);
+    std::vector<std::vector<double>> T(n, std::vector<double>(n, 0.0));
+    T[0][0] = 1.0;
+    if (n > 1) T[1][1] = 1.0;
+    for (int k = 1; k + 1 < n; ++k)
+        for (int j = 0; j < n; ++j) {
+            double v = -T[k - 1][j];
+            if (j > 0) v += 2.0 * T[k][j - 1];
+            T[k + 1][j] = v;
+        }
+    auto target = [&](int o, double th) {
+        const double w = window_value(win, method, m, beta, th + (m - 1 - o));
+        return o == 0 ? w / std::sqrt(1.0 - th) : w;
+    };
+    double worst = 0.0;
+    std::vector<double> mono(n);
+    for (int o = 0; o < m; ++o) {
+        std::vector<double> f(n), b(n, 0.0), d(n, 0.0);
+        for (int i = 0; i < n; ++i) f[i] = target(o, 0.5 * (std::cos(kPi * (i + 0.5) / n) + 1.0));
+        for (int k = 0; k < n; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) s += f[i] * std::cos(kPi * k * (i + 0.5) / n);
+            b[k] = (k == 0 ? 1.0 : 2.0) * s / n;
+        }
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j) d[j] += b[k] * T[k][j];
+        double p2 = 1.0;
+        for (int j = 0; j < n; ++j) {
+            mono[j] = d[j] * p2;   // x = 2t
+            p2 *= 2.0;
+        }
+        for (int j = 0; j < n; ++j)
+            (*coef)[size_t(o) * nc + (j % 2 == 0 ? j / 2 : n / 2 + j / 2)] = mono[j];
+        for (int qi = 0; qi <= 512; ++qi) {
+            const double th = qi / 512.0;
+            for (int side = 0; side < 2; ++side) {
+                const double t = side == 0 ? th - 0.5 : 0.5 - th;
+                double acc = 0.0;
+                for (int j = n - 1; j >= 0; --j) acc = acc * t + mono[j];
+                double wv;
+                if (o == 0) wv = acc * std::sqrt(side == 0 ? 1.0 - th : th);
+                else wv = acc;
+                const int oo = side == 0 ? o : 2 * m - 1 - o;
+                worst = std::max(worst, std::fabs(wv - window_value(win, method, m, beta, th + (m - 1 - oo))));
+            }
+        }
+    }
+    return worst;
+}
+
+// Per-stage twiddles w^{r k} = e^{2 pi i r k / (Ns R)}, laid out [k][r-1] for each stage
+// so that the R-1 values a butterfly needs are contiguous.  Stage s starts at off[s].
+void stage_twiddles(const FftFactors& fac, const std::vector<double>& tw, std::vector<double>* out,
+                    int* off) {
+    out->clear();
+    const int64_t L = fac.L;
+    int64_t Ns = 1;
+    for (int s = 0; s < fac.nstages; ++s) {
+        const int R = fac.radix[s];
+        off[s] = int(out->size() / 2);
+        if (Ns > 1) {
+            for (int64_t k = 0; k < Ns; ++k)
+                for (int r = 1; r < R; ++r) {
+                    const int64_t idx = (int64_t(r) * k * (L / (Ns * R))) % L;
+                    out->push_back(tw[2 * idx]);
+                    out->push_back(tw[2 * idx + 1]);
+                }
+        }
+        Ns *= R;
+    }
+}
+
+// Powers of two L >= 16: stages of the main radix E followed by at most one smaller power
+// of two (the stage plan the pass kernel is compiled for).
+bool factor_length(int L, int E, FftFactors* out) {
     out->L = L;
     out->nstages = 0;
-    if (L < 2 || (L & (L - 1)) != 0) return false;
+    if (L < 16 || (L & (L - 1)) != 0) return false;
     int rem = L;
-    while (rem > 1) {
-        int r = (rem % 16 == 0) ? 16 : (rem % 8 == 0) ? 8 : (rem % 4 == 0) ? 4 : 2;
+    while (rem % E == 0 && rem > 1) {
         if (out->nstages >= kMaxStages) return false;
-        out->radix[out->nstages++] = r;
-        rem /= r;
+        out->radix[out->nstages++] = E;
+        rem /= E;
     }
+    if (rem > 1) out->radix[out->nstages++] = rem;
     return true;
 }
 

@@ -16,6 +16,7 @@
 namespace bl {
 
 size_t gather_lds_bytes(const Plan& p);
+dev::WinF32 make_win_f32(const Plan& p);
 
 namespace {
 
@@ -32,6 +33,8 @@ struct SpreadArgs {
     int tile[3];
     int tpd[3];
     double beta, cb;
+    WinF32 wf;
+    float poly[kMaxM * kPolyCoef];
 };
 
 template <typename R>
@@ -60,7 +63,7 @@ __device__ __forceinline__ void tile_geometry(const int4& ch, const int* tpd, co
 
 template <typename R, int D, int M2, int METHOD>
 __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     R* acc = reinterpret_cast<R*>(smem_raw);   // interleaved re, im
     constexpr int m = M2 / 2;
     const int4 ch = a.chunks[blockIdx.x];
@@ -69,6 +72,10 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
     tile_geometry<D>(ch, a.tpd, a.tile, M2, n0, W);
     const int total = W[0] * W[1] * W[2];
     for (int e = threadIdx.x; e < 2 * total; e += blockDim.x) acc[e] = R(0);
+    float* coef = reinterpret_cast<float*>(smem_raw + ((size_t(total) * 2 * sizeof(R) + 15) & ~size_t(15)));
+    if constexpr (std::is_same<R, float>::value) {
+        for (int e = threadIdx.x; e < m * kPolyCoef; e += blockDim.x) coef[e] = a.poly[e];
+    }
     __syncthreads();
 
     const R* __restrict__ xs = static_cast<const R*>(a.xs);
@@ -77,14 +84,19 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
     for (int jj = threadIdx.x; jj < ch.z; jj += blockDim.x) {
         const int64_t j = int64_t(ch.y) + jj;
         R w[D][M2];
+        R theta[D];
         int r[3] = {0, 0, 0};
 #pragma unroll
         for (int t = 0; t < D; ++t) {
             int n;
-            R theta;
-            cell_of<R>(xs[j * D + t], L, n, theta);
+            cell_of<R>(xs[j * D + t], L, n, theta[t]);
             r[t] = n + L / 2 - n0[t];
-            weights<R, M2, METHOD>(theta, beta, cb, inv_m2, w[t]);
+        }
+        if constexpr (std::is_same<R, float>::value) {
+            weights_poly<D, M2, kPolyCoef>(theta, coef, w);
+        } else {
+#pragma unroll
+            for (int t = 0; t < D; ++t) weights<R, M2, METHOD>(theta[t], beta, cb, inv_m2, w[t]);
         }
         const Cx<R> gj = g[a.perm[j]];
         if constexpr (D == 1) {
@@ -313,6 +325,8 @@ SpreadArgs make_args(const Plan& p) {
     }
     a.beta = p.beta;
     a.cb = 1.0 / (-std::expm1(-2.0 * p.beta));
+    a.wf = make_win_f32(p);
+    for (size_t i = 0; i < p.poly.size() && i < size_t(kMaxM * kPolyCoef); ++i) a.poly[i] = p.poly[i];
     return a;
 }
 
@@ -337,7 +351,7 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
     SpreadArgs a = make_args(p);
     a.g = g;
     a.grid = grid;
-    const size_t lds = gather_lds_bytes(p);
+    const size_t lds = gather_lds_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);
