@@ -6,5 +6,7 @@ The transforms run in hand-written HIP kernels of ``libblnfft.so`` behind a C AB
 """
 from ._lib import BLNFFTError, EXPORTS, LIB_PATH, load  # noqa: F401
 from .plan import Plan, window_transform  # noqa: F401
+from .autograd import BandlimitedNFFT, bandlimited_nfft  # noqa: F401
 
-__all__ = ["Plan", "window_transform", "BLNFFTError", "load", "LIB_PATH", "EXPORTS"]
+__all__ = ["Plan", "window_transform", "BandlimitedNFFT", "bandlimited_nfft", "BLNFFTError",
+           "load", "LIB_PATH", "EXPORTS"]

@@ -67,7 +67,17 @@ void free_nodes(Plan& p) {
     p.chunk_alloc = 0;
 }
 
+void drop_graph(Plan& p) {
+    if (p.fwd_exec) hipGraphExecDestroy(p.fwd_exec);
+    p.fwd_exec = nullptr;
+    p.fwd_fhat = nullptr;
+    p.fwd_f = nullptr;
+}
+
 void free_plan(Plan& p) {
+    drop_graph(p);
+    if (p.capture_stream) hipStreamDestroy(p.capture_stream);
+    p.capture_stream = nullptr;
     free_nodes(p);
     hipFree(p.d_deconv);
     for (FftStages* st : {&p.st16, &p.st4}) {
@@ -114,6 +124,41 @@ void choose_tiles(Plan& p) {
         p.ntiles *= p.tiles_per_dim[t];
     }
     p.chunk_cap = 1024;
+}
+
+// Steps 1-3 as kernel launches on p.stream.
+bl_status forward_launches(Plan& p, const void* fhat, void* f) {
+    BL_TRY(launch_forward_fft(p, fhat));
+    return launch_gather(p, p.d_grid, f);
+}
+
+// Capture the forward launches into a graph on the private capture stream.
+bl_status capture_forward(Plan& p, const void* fhat, void* f) {
+    drop_graph(p);
+    if (!p.capture_stream) BL_HIP(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
+    hipStream_t user = p.stream;
+    p.stream = p.capture_stream;
+    hipError_t e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeThreadLocal);
+    bl_status st = BL_OK;
+    if (e == hipSuccess) st = forward_launches(p, fhat, f);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(p.capture_stream, &g);
+    p.stream = user;
+    if (e != hipSuccess || e2 != hipSuccess || st != BL_OK) {
+        if (g) hipGraphDestroy(g);
+        (void)hipGetLastError();
+        if (st != BL_OK) return st;
+        return fail(BL_EDEVICE, std::string("graph capture failed: ") +
+                                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(BL_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    p.fwd_exec = ge;
+    p.fwd_fhat = fhat;
+    p.fwd_f = f;
+    return BL_OK;
 }
 
 bl_status check_plan(bl_plan plan) {
@@ -195,6 +240,7 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     p.prec = prec;
     p.beta = (beta > 0.0) ? beta : default_beta(M, L, m, method);
     p.stream = static_cast<hipStream_t>(stream);
+    if (const char* e = std::getenv("BL_GRAPH")) p.use_graph = e[0] != '0';
     auto cleanup = [&](bl_status s) {
         free_plan(p);
         delete h;
@@ -291,6 +337,7 @@ bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev) {
     p.have_nodes = false;
     p.have_theta = false;
     p.N = 0;
+    drop_graph(p);
     const int64_t chunk_bound = N / p.chunk_cap + p.ntiles + 1;
     if (N > p.N_cap || chunk_bound > p.chunk_alloc) {
         BL_HIP(hipStreamSynchronize(p.stream));
@@ -317,9 +364,15 @@ bl_status bl_forward(bl_plan plan, const void* fhat_dev, void* f_dev) {
     Plan& p = plan->p;
     if (!p.have_nodes) return fail(BL_ESTATE, "bl_set_nodes must succeed before bl_forward");
     if (!fhat_dev || (p.N > 0 && !f_dev)) return fail(BL_EINVAL, "NULL buffer");
-    BL_TRY(launch_forward_fft(p, fhat_dev));
+    if (p.use_graph) {
+        if (!p.fwd_exec || p.fwd_fhat != fhat_dev || p.fwd_f != f_dev)
+            BL_TRY(capture_forward(p, fhat_dev, f_dev));
+        BL_HIP(hipGraphLaunch(p.fwd_exec, p.stream));
+    } else {
+        BL_TRY(forward_launches(p, fhat_dev, f_dev));
+    }
     p.have_theta = true;
-    return launch_gather(p, p.d_grid, f_dev);
+    return BL_OK;
 }
 
 bl_status bl_interpolate(bl_plan plan, const void* theta_dev, void* f_dev) {

@@ -118,6 +118,14 @@ struct Plan {
     bool have_theta = false;
     size_t workspace_bytes = 0;
 
+    // Forward transform captured as a hipGraph (on a private stream) and replayed on
+    // `stream`; valid for one (fhat, f) pointer pair and one node binding.
+    bool use_graph = true;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t fwd_exec = nullptr;
+    const void* fwd_fhat = nullptr;
+    void* fwd_f = nullptr;
+
     size_t real_size() const { return prec == BL_F64 ? 8 : 4; }
     size_t cplx_size() const { return 2 * real_size(); }
     int64_t grid_elems() const {

@@ -58,6 +58,8 @@ class Plan:
                   "bl_plan_create")
         self._h = h
         self.N = 0
+        self._nodes_version = 0
+        self._forward_version = 0
 
     # -- helpers
     def _check(self, t: torch.Tensor, shape, dtype, name: str):
@@ -88,6 +90,17 @@ class Plan:
         with self._dev():
             check(self._lib.bl_set_nodes(self.handle, N, _ptr(x)), "bl_set_nodes")
         self.N = N
+        self._nodes_version += 1
+
+    def bind_nodes(self, x: torch.Tensor) -> None:
+        """set_nodes, skipped when x is the tensor (same storage, shape and version) that
+        is bound already."""
+        key = (x.data_ptr(), tuple(x.shape), x._version, x.dtype)
+        if getattr(self, "_bound_key", None) == key and self._bound_nodes == self._nodes_version:
+            return
+        self.set_nodes(x)
+        self._bound_key = key
+        self._bound_nodes = self._nodes_version
 
     def forward(self, fhat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         self._check(fhat, (self.M,) * self.d, self.complex_dtype, "fhat")
@@ -96,7 +109,12 @@ class Plan:
         self._check(out, (self.N,), self.complex_dtype, "out")
         with self._dev():
             check(self._lib.bl_forward(self.handle, _ptr(fhat), _ptr(out)), "bl_forward")
+        self._forward_version += 1
         return out
+
+    def state(self) -> tuple:
+        """(node binding, forward) counters: identifies the samples theta the plan holds."""
+        return (self._nodes_version, self._forward_version)
 
     def interpolate(self, theta: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         self._check(theta, (self.L,) * self.d, self.complex_dtype, "theta")
