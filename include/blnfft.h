@@ -149,18 +149,33 @@ bl_status bl_plan_destroy(bl_plan plan);
 bl_status bl_window_transform(bl_window win, bl_method method, int64_t M, int64_t L, int m,
                               double beta, int64_t n, const double* v, double* out);
 
-/* Batched d = 1 transforms (Algorithm 4.2, BL_SHANNON, sinh window, default beta) of
- * `count` independent instances with their own (M_i, L_i, m_i, N_i), executed together.
- *   M, L, m, N : host arrays of length count (same rules as bl_plan_create per instance).
- *   prec       : BL_F32, BL_F32C or BL_F64.
- * Packed device buffers: instance i's fhat occupies sum_{i'<i} M_i' .. complex elements,
- * its nodes and outputs sum_{i'<i} N_i' ...  Synchronous. */
+/* Batched d = 1 transforms (Algorithm 4.2 with the sinh-type window of (2.5) and the
+ * default shape parameter beta = pi m (L - M) / L) of `count` independent instances with
+ * their own (M_i, L_i, m_i, N_i), executed as one graph launch: steps 1-2 of every
+ * instance in one kernel (one workgroup per instance, any even L_i via the chirp-z form of
+ * the length-L_i transform), step 3 of every instance in a second kernel.
+ *   M, L, m, N : host arrays of length count; per instance M even >= 2, L even > M,
+ *                2m < L, N >= 0 (else BL_EINVAL); 2 <= m <= 8 and L + M - 1 <= 32768
+ *                (else BL_EUNSUPPORTED).
+ *   prec       : BL_F32 or BL_F32C (float data; F32C adds compensated short sums);
+ *                BL_F64 gives BL_EUNSUPPORTED.
+ *   stream     : hipStream_t the calls are ordered on (NULL: default stream).
+ * Packed device buffers (complex = interleaved float pairs): instance i's fhat occupies
+ * complex elements [sum_{i'<i} M_i', +M_i) in the order k = -M_i/2 .. M_i/2 - 1, its nodes
+ * and outputs [sum_{i'<i} N_i', +N_i).  The batch owns its device workspace; the caller
+ * owns every buffer it passes.  Synchronous (builds the per-instance tables). */
 bl_status bl_batch_create(bl_batch* out, int count, const int64_t* M, const int64_t* L,
                           const int* m, const int64_t* N, bl_precision prec, void* stream);
-/* Bind the packed nodes (sum N_i reals).  Synchronizes once; BL_EDOMAIN as bl_set_nodes. */
+/* Bind the packed nodes (sum N_i floats in [-1/2, 1/2)); the pointer need not stay valid
+ * afterwards.  The first call times the short sums for a few tile sizes and keeps the
+ * fastest.  Synchronous; BL_EDOMAIN if a node is NaN/Inf or outside [-1/2, 1/2), after
+ * which forward calls fail with BL_ESTATE until a binding succeeds. */
 bl_status bl_batch_set_nodes(bl_batch batch, const void* x_dev);
-/* Forward transform of every instance: packed fhat in, packed f out.  Asynchronous. */
+/* Forward transform of every instance: packed fhat in, packed f out (both device).
+ * Asynchronous on the batch's stream; the first call with a new (fhat, f) pointer pair
+ * captures and instantiates the graph. */
 bl_status bl_batch_forward(bl_batch batch, const void* fhat_dev, void* f_dev);
+/* Synchronize the batch's stream and release everything the batch owns (NULL: no-op). */
 bl_status bl_batch_destroy(bl_batch batch);
 
 /* Status text (static storage) and the calling thread's last error message. */

@@ -145,6 +145,9 @@ double default_beta(int64_t M, int64_t L, int m, bl_method method);
 // Univariate transform of psi (shannon) or phi (nfft) at v, by the library's own
 // double-exponential quadrature.
 double window_transform(bl_window win, bl_method method, int64_t L, int m, double beta, double v);
+// The same at v = 0, 1, ..., K-1 (out has K entries).
+void window_transform_ints(bl_window win, bl_method method, int64_t L, int m, double beta, int64_t K,
+                           double* out);
 // e^{2 pi i n / L} for n in [0, L), correctly reduced; interleaved (re, im).
 void twiddles(int64_t L, std::vector<double>* out);
 bool factor_length(int L, int E, FftFactors* out);

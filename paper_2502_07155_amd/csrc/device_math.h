@@ -36,6 +36,9 @@ __device__ __forceinline__ float dev_floor(float v) { return floorf(v); }
 // grid [-L/2, L/2 - 1] (x = 1/2 - tiny can round L x up to L/2).
 template <typename R>
 __device__ __forceinline__ void cell_of(R x, int L, int& n, R& theta) {
+    // p - c must use the rounded product p: a contraction into fma(L, x, -c) would count
+    // the residual e twice.
+#pragma clang fp contract(off)
     R Lr = R(L);
     R p = Lr * x;
     R e = dev_fma(Lr, x, -p);
@@ -257,6 +260,8 @@ template <typename R>
 struct TwoSumAcc {
     R s_re = R(0), c_re = R(0), s_im = R(0), c_im = R(0);
     __device__ __forceinline__ static void step(R w, R v, R& s, R& c) {
+        // error-free transformations: no product may be fused into the sums
+#pragma clang fp contract(off)
         R p = w * v;
         R pe = dev_fma(w, v, -p);
         R t = s + p;

@@ -172,3 +172,80 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class BatchPlan:
+    """Many independent d = 1 transforms (Algorithm 4.2) with their own (M_i, L_i, m_i, N_i),
+    run together: one graph launch per forward call.
+
+    Packed buffers: fhat (sum M_i,) complex64, instance after instance, each in the order
+    k = -M_i/2 .. M_i/2 - 1; nodes (sum N_i,) float32; f (sum N_i,) complex64."""
+
+    def __init__(self, M, L, m, N, precision: str = "f32", device=None, stream=None):
+        self._lib = load()
+        self.M = [int(v) for v in M]
+        self.L = [int(v) for v in L]
+        self.m = [int(v) for v in m]
+        self.N = [int(v) for v in N]
+        if not (len(self.M) == len(self.L) == len(self.m) == len(self.N)):
+            raise ValueError("M, L, m and N must have the same length")
+        self.count = len(self.M)
+        self.precision = precision
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.fhat_offsets = np.concatenate([[0], np.cumsum(self.M)]).astype(np.int64)
+        self.node_offsets = np.concatenate([[0], np.cumsum(self.N)]).astype(np.int64)
+        self.total_M = int(self.fhat_offsets[-1])
+        self.total_N = int(self.node_offsets[-1])
+        i64 = ctypes.c_int64 * max(self.count, 1)
+        i32 = ctypes.c_int * max(self.count, 1)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            check(self._lib.bl_batch_create(ctypes.byref(h), self.count, i64(*self.M), i64(*self.L),
+                                            i32(*self.m), i64(*self.N), PRECISIONS[precision],
+                                            ctypes.c_void_p(self.stream.cuda_stream)),
+                  "bl_batch_create")
+        self._h = h
+
+    def _check(self, t: torch.Tensor, n: int, dtype, name: str):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.device != self.device or t.dtype != dtype or tuple(t.shape) != (n,) \
+                or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous ({n},) {dtype} tensor on {self.device}")
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("batch destroyed")
+        return self._h
+
+    def set_nodes(self, x: torch.Tensor) -> None:
+        self._check(x, self.total_N, torch.float32, "x")
+        with torch.cuda.device(self.device):
+            check(self._lib.bl_batch_set_nodes(self.handle, _ptr(x)), "bl_batch_set_nodes")
+
+    def forward(self, fhat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._check(fhat, self.total_M, torch.complex64, "fhat")
+        if out is None:
+            out = torch.empty(self.total_N, dtype=torch.complex64, device=self.device)
+        self._check(out, self.total_N, torch.complex64, "out")
+        with torch.cuda.device(self.device):
+            check(self._lib.bl_batch_forward(self.handle, _ptr(fhat), _ptr(out)), "bl_batch_forward")
+        return out
+
+    def split(self, f: torch.Tensor) -> list:
+        """Per-instance views of a packed output."""
+        return [f[self.node_offsets[i]:self.node_offsets[i + 1]] for i in range(self.count)]
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            self._lib.bl_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -77,6 +77,42 @@ def test_plan_create_rejects_before_device_use(lib, kw, status):
     assert len(lib.bl_last_error()) > 0
 
 
+def _batch_create(lib, spec, prec=1):
+    n = len(spec)
+    i64 = ctypes.c_int64 * max(n, 1)
+    i32 = ctypes.c_int * max(n, 1)
+    h = ctypes.c_void_p()
+    st = lib.bl_batch_create(ctypes.byref(h), n, i64(*[s[0] for s in spec]), i64(*[s[1] for s in spec]),
+                             i32(*[s[2] for s in spec]), i64(*[s[3] for s in spec]), prec, None)
+    return st, h
+
+
+@pytest.mark.parametrize("spec,prec,status", [
+    ([], 1, 1),                                            # no instance
+    ([(64, 128, 4, 10)], 0, 6),                            # FP64 batches unsupported
+    ([(64, 128, 4, 10)], 9, 1),                            # unknown precision
+    ([(64, 128, 4, 10), (63, 128, 4, 10)], 1, 1),          # odd M
+    ([(64, 64, 4, 10)], 1, 1),                             # L = M: default beta is zero
+    ([(64, 130, 4, 10), (64, 127, 4, 10)], 2, 1),          # odd L
+    ([(8, 16, 8, 10)], 1, 1),                              # 2m >= L
+    ([(64, 128, 4, -1)], 1, 1),                            # negative N
+    ([(64, 128, 9, 10)], 1, 6),                            # m above the kernels' range
+    ([(64, 128, 1, 10)], 1, 6),                            # m below it
+    ([(10000, 24000, 4, 10)], 1, 6),                       # L + M - 1 above 32768
+])
+def test_batch_create_rejects_before_device_use(lib, spec, prec, status):
+    st, h = _batch_create(lib, spec, prec)
+    assert st == status
+    assert h.value is None
+    assert len(lib.bl_last_error()) > 0
+
+
+def test_batch_calls_with_null_handle(lib):
+    assert lib.bl_batch_set_nodes(None, None) == 1
+    assert lib.bl_batch_forward(None, None, None) == 1
+    assert lib.bl_batch_destroy(None) == 0
+
+
 def test_calls_with_null_plan(lib):
     assert lib.bl_set_nodes(None, 10, None) == 1
     assert lib.bl_forward(None, None, None) == 1

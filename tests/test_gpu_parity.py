@@ -55,6 +55,9 @@ SMALL = [
     (2, 48, 64, 8, 2000),
     (3, 16, 32, 4, 3000),
     (3, 24, 32, 2, 1500),
+    (1, 2048, 4096, 6, 3000),     # 1-D lines above 2048 points: radix-16 passes
+    (1, 4096, 8192, 8, 2000),     # the longest supported line
+    (2, 512, 2048, 4, 3000),
 ]
 
 
