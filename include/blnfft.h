@@ -61,8 +61,9 @@ typedef enum {
     BL_F32 = 1,           /* float data and arithmetic, FP64-derived twiddles/factors   */
     BL_F32C = 2           /* float inputs, outputs and grid of samples; the FFT passes
                              compute in double with double intermediates (one rounding,
-                             at the store of the grid); short sums with float weights and
-                             compensated (error-free product + two-sum) accumulation   */
+                             at the store of the grid); short sums with float weights,
+                             inner sums in float and the outermost sum accumulated in
+                             double (float products are exact in double)              */
 } bl_precision;
 
 typedef struct bl_plan_s* bl_plan;
@@ -157,7 +158,7 @@ bl_status bl_window_transform(bl_window win, bl_method method, int64_t M, int64_
  *   M, L, m, N : host arrays of length count; per instance M even >= 2, L even > M,
  *                2m < L, N >= 0 (else BL_EINVAL); 2 <= m <= 8 and L + M - 1 <= 32768
  *                (else BL_EUNSUPPORTED).
- *   prec       : BL_F32 or BL_F32C (float data; F32C adds compensated short sums);
+ *   prec       : BL_F32 or BL_F32C (float data; F32C accumulates the short sums in double);
  *                BL_F64 gives BL_EUNSUPPORTED.
  *   stream     : hipStream_t the calls are ordered on (NULL: default stream).
  * Packed device buffers (complex = interleaved float pairs): instance i's fhat occupies

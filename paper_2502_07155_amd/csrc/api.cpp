@@ -21,8 +21,6 @@ thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 const std::string& last_error() { return g_err; }
 
-size_t gather_lds_bytes(const Plan& p);
-
 namespace {
 
 bl_status fail(bl_status s, const std::string& msg) {

@@ -348,7 +348,7 @@ __device__ __forceinline__ void bgather_nodes(const BGatherArgs& a, const int4& 
         const int r = n + d.L / 2 - n0;
         float w[1][M2];
         dev::weights_poly<1, M2, kPolyCoef>(theta, coef, w);
-        typename std::conditional<ACC == 1, dev::TwoSumAcc<float>, dev::Plain<float>>::type acc;
+        typename std::conditional<ACC == 1, dev::WideAcc<float>, dev::Plain<float>>::type acc;
 #pragma unroll
         for (int o = 0; o < M2; ++o) acc.add(w[0][o], lds[r + o]);
         f[a.perm[j]] = acc.value();

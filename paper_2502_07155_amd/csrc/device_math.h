@@ -254,34 +254,18 @@ struct Plain {
     __device__ __forceinline__ Cx<R> value() const { return {re, im}; }
 };
 
-// Compensated dot product (error-free product by fma, two-sum accumulation): the running
-// sum s and a correction c collecting every rounding error of products and sums.
+// Wide accumulation of float terms: each product of two floats is exact in double, and the
+// running sum is kept in double, so the only rounding of the sum is the final one to the
+// working precision.  For double data it is the plain FMA sum.
 template <typename R>
-struct TwoSumAcc {
-    R s_re = R(0), c_re = R(0), s_im = R(0), c_im = R(0);
-    __device__ __forceinline__ static void step(R w, R v, R& s, R& c) {
-        // error-free transformations: no product may be fused into the sums
-#pragma clang fp contract(off)
-        R p = w * v;
-        R pe = dev_fma(w, v, -p);
-        R t = s + p;
-        R z = t - s;
-        R se = (s - (t - z)) + (p - z);
-        s = t;
-        c += pe + se;
-    }
+struct WideAcc {
+    double re = 0.0, im = 0.0;
     __device__ __forceinline__ void add(R w, Cx<R> v) {
-        step(w, v.re, s_re, c_re);
-        step(w, v.im, s_im, c_im);
+        const double wd = double(w);
+        re = fma(wd, double(v.re), re);
+        im = fma(wd, double(v.im), im);
     }
-    // weight given as the unevaluated sum w + wl (wl: rounding error of a weight product)
-    __device__ __forceinline__ void add2(R w, R wl, Cx<R> v) {
-        step(w, v.re, s_re, c_re);
-        step(w, v.im, s_im, c_im);
-        c_re = dev_fma(wl, v.re, c_re);
-        c_im = dev_fma(wl, v.im, c_im);
-    }
-    __device__ __forceinline__ Cx<R> value() const { return {s_re + c_re, s_im + c_im}; }
+    __device__ __forceinline__ Cx<R> value() const { return {R(re), R(im)}; }
 };
 
 

@@ -242,40 +242,57 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
             W[t] = a.tile[t] + M2 - 1;
         }
     }
-    const int total = W[0] * W[1] * W[2];
     // LDS strides: dimension t advances by S[t] elements; the innermost row is padded to
     // a.pitch[D-1] elements.
     int S[3] = {1, 1, 1};
     if (D >= 2) S[D - 2] = a.pitch[D - 1];
     if (D >= 3) S[0] = S[1] * W[1];
-    const int lds_elems = S[0] * W[0];
+    // d = 2 float tiles are stored twice, the second copy shifted by one element, so that
+    // every node's rows start 16-byte aligned in one of them and are read with 128-bit
+    // loads (the row pitch is even).
+    constexpr bool kDual = D == 2 && std::is_same<R, float>::value;
+    const int one_copy = kDual ? ((S[0] * W[0] + 1) & ~1) : S[0] * W[0];
+    const int lds_elems = kDual ? 2 * one_copy : one_copy;
+    Cx<R>* ldsB = lds + one_copy;
     const Cx<R>* __restrict__ th = static_cast<const Cx<R>*>(a.theta);
     // float weight polynomials after the tile in LDS, 16-byte aligned
     float* coef = reinterpret_cast<float*>(smem_raw + ((size_t(lds_elems) * sizeof(Cx<R>) + 15) & ~size_t(15)));
     if constexpr (std::is_same<R, float>::value && M2 > 12) {
         for (int e = threadIdx.x; e < m * kPolyCoef; e += blockDim.x) coef[e] = a.poly[e];
     }
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    // Stage the tile plus halo.  Element e of a power-of-two padded box is split into
+    // per-dimension coordinates with shifts and masks (no integer division); padding
+    // coordinates beyond W[t] are skipped.  Grid indices fit in 32 bits (L^d <= 2^31).
+    int lgw[3] = {0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+        while ((1 << lgw[t]) < W[t]) ++lgw[t];
+    const int lg_total = lgw[0] + (D >= 2 ? lgw[1] : 0) + (D >= 3 ? lgw[2] : 0);
+    for (int e = threadIdx.x; e < (1 << lg_total); e += blockDim.x) {
         int rem = e;
-        int64_t gidx = 0;
         int li = 0;
-        bool ok = true;
+        uint32_t gidx = 0, gstride = 1;
+        bool inbox = true, ingrid = true;
 #pragma unroll
         for (int t = D - 1; t >= 0; --t) {
-            int ct = rem % W[t];
-            rem /= W[t];
+            const int ct = rem & ((1 << lgw[t]) - 1);
+            rem >>= lgw[t];
+            inbox = inbox && ct < W[t];
             li += ct * S[t];
             int p = n0[t] - m + 1 + ct;   // cell index of this grid point
             if (METHOD == 1) {
-                p = (p % L + L) % L;
+                p &= L - 1;               // periodic; L is a power of two
             } else if (p < 0 || p >= L) {
-                ok = false;
+                ingrid = false;
             }
-            int64_t st = 1;
-            for (int s = t + 1; s < D; ++s) st *= L;
-            gidx += int64_t(p) * st;
+            gidx += uint32_t(p) * gstride;   // the last dimension is the fastest
+            gstride *= uint32_t(L);
         }
-        lds[li] = ok ? th[gidx] : Cx<R>{R(0), R(0)};
+        if (inbox) {
+            const Cx<R> v = ingrid ? th[gidx] : Cx<R>{R(0), R(0)};
+            lds[li] = v;
+            if (kDual && li > 0) ldsB[li - 1] = v;
+        }
     }
     __syncthreads();
 
@@ -303,8 +320,8 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
                 weights<R, M2, METHOD>(theta[t], R(a.beta), R(a.cb), R(1) / R(m * m), w[t]);
         }
         // Separable contraction: plain FMA sums along the last dimension(s); with ACC == 1
-        // the outermost sum is compensated (error-free products and two-sum).
-        using Outer = typename std::conditional<ACC == 1, TwoSumAcc<R>, Plain<R>>::type;
+        // the outermost sum is accumulated in double (float products are exact there).
+        using Outer = typename std::conditional<ACC == 1, WideAcc<R>, Plain<R>>::type;
         Cx<R> res;
         if constexpr (D == 1) {
             Outer acc;
@@ -314,13 +331,29 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
         } else if constexpr (D == 2) {
             const int base = r[0] * S[0] + r[1];
             Outer acc;
+            if constexpr (kDual) {
+                const Cx<R>* src = (base & 1) ? ldsB + (base - 1) : lds + base;
 #pragma unroll
-            for (int o0 = 0; o0 < M2; ++o0) {
-                const Cx<R>* row = lds + base + o0 * S[0];
-                Plain<R> racc;
+                for (int o0 = 0; o0 < M2; ++o0) {
+                    const float4* row = reinterpret_cast<const float4*>(src + o0 * S[0]);
+                    Plain<R> racc;
 #pragma unroll
-                for (int o1 = 0; o1 < M2; ++o1) racc.add(w[1][o1], row[o1]);
-                acc.add(w[0][o0], racc.value());
+                    for (int q = 0; q < M2 / 2; ++q) {
+                        const float4 v = row[q];
+                        racc.add(w[1][2 * q], Cx<R>{v.x, v.y});
+                        racc.add(w[1][2 * q + 1], Cx<R>{v.z, v.w});
+                    }
+                    acc.add(w[0][o0], racc.value());
+                }
+            } else {
+#pragma unroll
+                for (int o0 = 0; o0 < M2; ++o0) {
+                    const Cx<R>* row = lds + base + o0 * S[0];
+                    Plain<R> racc;
+#pragma unroll
+                    for (int o1 = 0; o1 < M2; ++o1) racc.add(w[1][o1], row[o1]);
+                    acc.add(w[0][o0], racc.value());
+                }
             }
             res = acc.value();
         } else {
@@ -393,23 +426,35 @@ dev::WinF32 make_win_f32(const Plan& p) {
 // LDS pitch (elements) of the staged tile's innermost row.  Rows are padded so that a
 // row step moves by half of the 64 LDS banks: lanes reading neighbouring tile rows then
 // fall on disjoint banks.
+bool dual_tile(const Plan& p) { return p.d == 2 && p.prec != BL_F64; }
+
 int tile_pitch(const Plan& p) {
     const int w = p.tile[p.d - 1] + 2 * p.m - 1;
     int mode = 1;
     if (const char* e = std::getenv("BL_PITCH")) mode = std::atoi(e);   // tuning override
-    if (p.d == 1 || mode == 0) return w;
-    if (mode == 2) return w | 1;
-    if (p.d != 2) return w;   // measured: padding helps d = 2 tiles, not d = 3
-    const int words = int(p.cplx_size() / 4);   // 32-bit banks per element
-    for (int q = w; q < w + 64; ++q)
-        if ((q * words) % 64 == 32) return q;
-    return w;
+    int q = w;
+    if (p.d == 1 || mode == 0) {
+        q = w;
+    } else if (mode == 2) {
+        q = w | 1;
+    } else if (p.d == 2) {   // measured: padding helps d = 2 tiles, not d = 3
+        const int words = int(p.cplx_size() / 4);   // 32-bit banks per element
+        for (int c = w; c < w + 64; ++c)
+            if ((c * words) % 64 == 32) {
+                q = c;
+                break;
+            }
+    }
+    if (dual_tile(p)) q = (q + 1) & ~1;   // 128-bit row reads need an even pitch
+    return q;
 }
 
+// LDS bytes of the staged tile (both copies for dual tiles), 16-byte multiple.
 size_t gather_lds_bytes(const Plan& p) {
     size_t e = size_t(tile_pitch(p));
     for (int t = 0; t + 1 < p.d; ++t) e *= size_t(p.tile[t] + 2 * p.m - 1);
-    return e * p.cplx_size();
+    if (dual_tile(p)) e = 2 * ((e + 1) & ~size_t(1));
+    return (e * p.cplx_size() + 15) & ~size_t(15);
 }
 
 bl_status launch_binning(Plan& p, const void* x, int64_t N) {

@@ -15,7 +15,12 @@
 
 namespace bl {
 
-size_t gather_lds_bytes(const Plan& p);
+// LDS bytes of one unpadded tile-plus-halo box of the plan's complex type, 16-byte multiple.
+size_t box_bytes(const Plan& p) {
+    size_t e = 1;
+    for (int t = 0; t < p.d; ++t) e *= size_t(p.tile[t] + 2 * p.m - 1);
+    return (e * p.cplx_size() + 15) & ~size_t(15);
+}
 dev::WinF32 make_win_f32(const Plan& p);
 
 namespace {
@@ -351,7 +356,7 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
     SpreadArgs a = make_args(p);
     a.g = g;
     a.grid = grid;
-    const size_t lds = gather_lds_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
+    const size_t lds = box_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);
@@ -370,7 +375,7 @@ bl_status launch_grad_x(Plan& p, const void* g, void* gx) {
     a.g = g;
     a.grid = p.d_grid;
     a.gx = gx;
-    const size_t lds = gather_lds_bytes(p);
+    const size_t lds = box_bytes(p);
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);

@@ -35,7 +35,8 @@ def window_transform(v, M: int, L: int, m: int, beta: float = 0.0, window: str =
 class Plan:
     """One transform configuration (Algorithm 4.2 or Algorithm 2.1) on one device/stream.
 
-    precision: "f64", "f32" or "f32c" (FP32 with compensated short sums).
+    precision: "f64", "f32" or "f32c" (float data, FP64 FFT arithmetic and FP64
+    accumulation of the short sums).
     Inputs/outputs are torch tensors on the plan's device: fhat (M,)*d complex, nodes (N, d)
     real, f (N,) complex, in the plan's precision."""
 
