@@ -278,6 +278,9 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
         std::vector<double> pc;
         p.poly_err = fit_weight_polys(win, method, m, p.beta, kPolyCoef, &pc);
         p.poly.assign(pc.begin(), pc.end());
+    } else {
+        p.poly64_err = fit_weight_polys(win, method, m, p.beta, kPolyCoef64, &p.poly64);
+        p.use_poly64 = p.poly64_err <= 1e-13 && std::getenv("BL_EXACT_WEIGHTS") == nullptr;
     }
 
     size_t total = 0;

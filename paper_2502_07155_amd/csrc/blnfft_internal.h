@@ -35,6 +35,7 @@ constexpr int kMaxStages = 16;
 constexpr int kMinM = 2;    // truncation range of the compiled short-sum kernels
 constexpr int kMaxM = 8;
 constexpr int kPolyCoef = 12;   // coefficients of the float weight polynomials (degree 11)
+constexpr int kPolyCoef64 = 16; // coefficients of the double weight polynomials (degree 15)
 
 // Factorisation of one FFT length into Stockham stages.
 struct FftFactors {
@@ -85,6 +86,11 @@ struct Plan {
     // largest deviation of the fitted weights from the exact ones.
     std::vector<float> poly;
     double poly_err = 0.0;
+    // The same in double with kPolyCoef64 coefficients (BL_F64 plans), used when the fit
+    // is within 1e-13 of the exact weights; otherwise the kernels evaluate them exactly.
+    std::vector<double> poly64;
+    double poly64_err = 0.0;
+    bool use_poly64 = false;
     // Inverse-direction twiddles for the adjoint are the conjugates; computed in kernel.
 
     // FFT ping-pong buffers and the grid of theta (L^d complex).

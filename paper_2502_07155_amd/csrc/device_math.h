@@ -243,6 +243,47 @@ __device__ __forceinline__ void weights_poly(const float* theta, const float* co
     }
 }
 
+// Double weights from polynomials in the same even/odd layout as weights_poly (NC/2 even
+// then NC/2 odd coefficients per offset pair, read from LDS as uniform double2 loads).
+template <int D, int M2, int NC>
+__device__ __forceinline__ void weights_poly64(const double* theta, const double* coef,
+                                               double (*w)[M2]) {
+    constexpr int m = M2 / 2;
+    constexpr int NE = NC / 2;
+    static_assert(NC % 2 == 0 && NE % 2 == 0, "coefficients are read as double2");
+    // dimension-major, so that only one offset's coefficients are live at a time
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double t = theta[d] - 0.5, t2 = t * t;
+#pragma unroll
+        for (int o = 0; o < m; ++o) {
+            const double2* c2 = reinterpret_cast<const double2*>(coef + o * NC);
+            double2 top = c2[NE / 2 - 1], topo = c2[NC / 2 - 1];
+            double E = top.y, Od = topo.y;
+            E = fma(E, t2, top.x);
+            Od = fma(Od, t2, topo.x);
+#pragma unroll
+            for (int q = NE / 2 - 2; q >= 0; --q) {
+                const double2 ce = c2[q], co = c2[NE / 2 + q];
+                E = fma(fma(E, t2, ce.y), t2, ce.x);
+                Od = fma(fma(Od, t2, co.y), t2, co.x);
+            }
+            const double tO = t * Od;
+            const double p = E + tO, q = E - tO;
+            if (o == 0) {
+                w[d][0] = sqrt(1.0 - theta[d]) * p;
+                w[d][M2 - 1] = sqrt(theta[d]) * q;
+            } else {
+                w[d][o] = p;
+                w[d][M2 - 1 - o] = q;
+            }
+            // keep each polynomial's coefficient loads next to their use (bounded
+            // register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- accumulators
 template <typename R>
 struct Plain {

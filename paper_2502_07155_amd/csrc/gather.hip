@@ -218,9 +218,12 @@ struct GatherArgs {
     int tile[3];
     int tpd[3];
     int pitch[3];          // LDS pitch (elements) of each tile dimension
+    uint32_t wdiv[3];      // floor(2^20 / W) + 1 for each box extent W = tile + 2m - 1
     double beta, cb;
     WinF32 wf;             // float window constants
     alignas(16) float poly[kMaxM * kPolyCoef];   // float weight polynomials (see weights_poly)
+    alignas(16) double poly64[kMaxM * kPolyCoef64];   // double ones (see weights_poly64)
+    int use_poly64;
 };
 
 template <typename R, int D, int M2, int ACC, int METHOD>
@@ -260,38 +263,61 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
     if constexpr (std::is_same<R, float>::value && M2 > 12) {
         for (int e = threadIdx.x; e < m * kPolyCoef; e += blockDim.x) coef[e] = a.poly[e];
     }
-    // Stage the tile plus halo.  Element e of a power-of-two padded box is split into
-    // per-dimension coordinates with shifts and masks (no integer division); padding
-    // coordinates beyond W[t] are skipped.  Grid indices fit in 32 bits (L^d <= 2^31).
-    int lgw[3] = {0, 0, 0};
+    double* coef64 = reinterpret_cast<double*>(coef);
+    if constexpr (std::is_same<R, double>::value) {
+        if (a.use_poly64)
+            for (int e = threadIdx.x; e < m * kPolyCoef64; e += blockDim.x) coef64[e] = a.poly64[e];
+    }
+    // Stage the tile plus halo.  Element e of the box is split into per-dimension
+    // coordinates by multiplying with wdiv[t] = floor(2^20 / W[t]) + 1 (exact division
+    // while e * W[t] < 2^20, which the 64 KB tile budget guarantees).  Grid indices fit in
+    // 32 bits (L^d <= 2^31).
+    // Loads are issued kStage at a time per thread before their LDS writes, so that
+    // several are in flight at once.
+    constexpr int kStage = 4;
+    const int total = W[0] * W[1] * W[2];
+    for (int e0 = threadIdx.x; e0 < total; e0 += kStage * blockDim.x) {
+        Cx<R> v[kStage];
+        int lis[kStage];
 #pragma unroll
-    for (int t = 0; t < D; ++t)
-        while ((1 << lgw[t]) < W[t]) ++lgw[t];
-    const int lg_total = lgw[0] + (D >= 2 ? lgw[1] : 0) + (D >= 3 ? lgw[2] : 0);
-    for (int e = threadIdx.x; e < (1 << lg_total); e += blockDim.x) {
-        int rem = e;
-        int li = 0;
-        uint32_t gidx = 0, gstride = 1;
-        bool inbox = true, ingrid = true;
+        for (int u = 0; u < kStage; ++u) {
+            const int e = e0 + u * int(blockDim.x);
+            lis[u] = -1;
+            v[u] = Cx<R>{R(0), R(0)};
+            if (e < total) {
+                uint32_t rem = uint32_t(e);
+                int li = 0;
+                uint32_t gidx = 0, gstride = 1;
+                bool ingrid = true;
 #pragma unroll
-        for (int t = D - 1; t >= 0; --t) {
-            const int ct = rem & ((1 << lgw[t]) - 1);
-            rem >>= lgw[t];
-            inbox = inbox && ct < W[t];
-            li += ct * S[t];
-            int p = n0[t] - m + 1 + ct;   // cell index of this grid point
-            if (METHOD == 1) {
-                p &= L - 1;               // periodic; L is a power of two
-            } else if (p < 0 || p >= L) {
-                ingrid = false;
+                for (int t = D - 1; t >= 0; --t) {
+                    int ct;
+                    if (t > 0) {
+                        const uint32_t q = uint32_t((uint64_t(rem) * a.wdiv[t]) >> 20);
+                        ct = int(rem - q * uint32_t(W[t]));
+                        rem = q;
+                    } else {
+                        ct = int(rem);
+                    }
+                    li += ct * S[t];
+                    int p = n0[t] - m + 1 + ct;   // cell index of this grid point
+                    if (METHOD == 1) {
+                        p &= L - 1;               // periodic; L is a power of two
+                    } else if (p < 0 || p >= L) {
+                        ingrid = false;
+                    }
+                    gidx += uint32_t(p) * gstride;   // the last dimension is the fastest
+                    gstride *= uint32_t(L);
+                }
+                lis[u] = li;
+                if (ingrid) v[u] = th[gidx];
             }
-            gidx += uint32_t(p) * gstride;   // the last dimension is the fastest
-            gstride *= uint32_t(L);
         }
-        if (inbox) {
-            const Cx<R> v = ingrid ? th[gidx] : Cx<R>{R(0), R(0)};
-            lds[li] = v;
-            if (kDual && li > 0) ldsB[li - 1] = v;
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            if (lis[u] < 0) continue;
+            lds[lis[u]] = v[u];
+            if (kDual && lis[u] > 0) ldsB[lis[u] - 1] = v[u];
         }
     }
     __syncthreads();
@@ -314,6 +340,12 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
             // would spill SGPRs, so those read them from LDS (broadcast).
             if constexpr (M2 <= 12) weights_poly<D, M2, kPolyCoef>(theta, a.poly, w);
             else weights_poly<D, M2, kPolyCoef>(theta, coef, w);
+        } else if (a.use_poly64) {
+            // An opaque zero offset keeps the (uniform, LDS) coefficient loads inside the
+            // node loop instead of holding every coefficient in registers.
+            int opaque = 0;
+            asm volatile("" : "+s"(opaque));
+            weights_poly64<D, M2, kPolyCoef64>(theta, coef64 + opaque, w);
         } else {
 #pragma unroll
             for (int t = 0; t < D; ++t)
@@ -359,8 +391,14 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
         } else {
             const int base = r[0] * S[0] + r[1] * S[1] + r[2];
             Outer acc;
+            // The o0 loop stays rolled (code size); its weight is taken from the front of
+            // a register array shifted each iteration, not by a dynamic index (which
+            // would place the array in scratch memory).
 #pragma unroll 1
             for (int o0 = 0; o0 < M2; ++o0) {
+                const R w0 = w[0][0];
+#pragma unroll
+                for (int k = 0; k + 1 < M2; ++k) w[0][k] = w[0][k + 1];
                 Plain<R> pacc;
 #pragma unroll
                 for (int o1 = 0; o1 < M2; ++o1) {
@@ -370,7 +408,7 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
                     for (int o2 = 0; o2 < M2; ++o2) racc.add(w[2][o2], row[o2]);
                     pacc.add(w[1][o1], racc.value());
                 }
-                acc.add(w[0][o0], pacc.value());
+                acc.add(w0, pacc.value());
             }
             res = acc.value();
         }
@@ -575,12 +613,15 @@ bl_status launch_gather(Plan& p, const void* theta, void* f) {
         a.tile[t] = p.tile[t];
         a.tpd[t] = p.tiles_per_dim[t];
         a.pitch[t] = (t == p.d - 1) ? tile_pitch(p) : (t < p.d ? p.tile[t] + 2 * p.m - 1 : 1);
+        a.wdiv[t] = (1u << 20) / uint32_t(p.tile[t] + 2 * p.m - 1) + 1u;
     }
     a.beta = p.beta;
     a.cb = 1.0 / (-std::expm1(-2.0 * p.beta));
     a.wf = make_win_f32(p);
     for (size_t i = 0; i < p.poly.size() && i < size_t(kMaxM * kPolyCoef); ++i) a.poly[i] = p.poly[i];
-    const size_t lds = gather_lds_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
+    for (size_t i = 0; i < p.poly64.size() && i < size_t(kMaxM * kPolyCoef64); ++i) a.poly64[i] = p.poly64[i];
+    a.use_poly64 = p.use_poly64 ? 1 : 0;
+    const size_t lds = gather_lds_bytes(p) + 16 + sizeof(double) * kMaxM * kPolyCoef64;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);
