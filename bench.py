@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-nodes", type=int, default=1_000_000,
                     help="nodes of the oracle's step-3 sample for the CPU baseline")
+    ap.add_argument("--leg", choices=["batched", "fwd_bwd", "nfft"],
+                    help="run only this leg (batched d=1 instances, d=2 forward + backward, or "
+                         "Algorithm 2.1 on the headline workload) and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (for counter scaling)")
     ap.add_argument("--summarize-trace", metavar="DIR",
@@ -355,6 +358,17 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.leg == "batched":
+        print(json.dumps(leg_batched(args.steps, args.warmup)))
+        return
+    if args.leg == "fwd_bwd":
+        print(json.dumps(leg_differentiation(args.steps, args.warmup)))
+        return
+    if args.leg == "nfft":
+        p, plan, f, _, _, _ = run_plan(HEADLINE, "f32c", 2, 1)
+        plan.close()
+        print(json.dumps(leg_nfft(args.steps, args.warmup, f, p)))
         return
 
     prec = args.precision
