@@ -10,8 +10,9 @@
 //   theta_l = u^{l^2} z[l mod P].
 // a_k = fhat(k) / (L psihat(k)) (step 1) and the chirps u^{k^2}, u^{l^2} are formed in FP64 on
 // the host (k^2 mod 2L in integers); H is computed on the host in FP64 and stored as float.
-// One workgroup per instance runs its two DFTs in LDS (size P <= 16384); for P = 32768 one
-// radix-2 split through global scratch reduces them to four LDS DFTs of P/2.
+// Each length-P DFT pair is split into R = P / S pieces of S <= 4096 points (a radix-R
+// decimation in frequency through global scratch); one 256-thread workgroup per piece
+// runs its two DFTs in LDS, and the last piece of an instance to finish combines them.
 //
 // Step 3 runs one workgroup per work chunk of the instances' node tiles, as in the
 // single-transform short sums, with each chunk's instance parameters (L, m, window
@@ -36,33 +37,54 @@ namespace {
 namespace sk = stockham;
 using CxF = dev::Cx<float>;
 
-constexpr int kBatchThreads = 1024;
-constexpr int kMaxLdsFft = 16384;      // largest DFT held in LDS (float complex)
+constexpr int kBatchThreads = 512;
+constexpr int kMaxLdsFft = 8192;       // largest DFT held in LDS (float complex)
 constexpr int kMaxP = 32768;
 
 struct InstDesc {
     int M, L, m, P;
-    int split;           // 1: P = 2 S, one radix-2 split through scratch
+    int R;               // P = R S: R pieces of S points (R = 1: one LDS DFT)
     int lgS;             // log2 of the LDS DFT size S (P or P/2)
     int tw_off;          // twiddle table e^{2 pi i n / S}, n < S
-    int twP_off;         // twiddle table e^{2 pi i n / P}, n < P (split instances)
+    int twP_off;         // twiddle table e^{2 pi i n / P}, n < P (R > 1)
     long long fhat_off;  // band samples (M complex)
     long long theta_off; // samples theta (L complex, centred)
     long long pre_off;   // a-factor times chirp, M double complex
     long long post_off;  // chirp u^{l^2}, L double complex
     long long h_off;     // H, P float complex
-    long long scr_off;   // scratch (P float complex) for split instances
+    long long scr_off;   // scratch (P float complex) for R > 1
     long long node_off;  // first node of the instance
     int tile_base;       // first global tile of the instance
     int ntiles;
 };
 
 // ---------------------------------------------------------------- LDS DFT
-// In-place radix-4 (+ a final radix-2) Stockham DFT of size S = 2^lgS on an LDS buffer
-// indexed through padpos; kBatchThreads threads, up to 16 values each per stage.
+// Twiddles e^{2 pi i n / S} from two small LDS tables: hi[n >> 7] * lo[n & 127].
+struct Roots {
+    const sk::Cx<float>* hi;
+    const sk::Cx<float>* lo;
+    __device__ __forceinline__ sk::Cx<float> operator[](int n) const {
+        return sk::cmul(hi[n >> 7], lo[n & 127]);
+    }
+};
+constexpr int kRootLo = 128;
+constexpr int kRootHi = kMaxLdsFft / kRootLo;
+
+// Stage the two tables of S-th roots from the full table tw (S entries) into LDS.
+__device__ __forceinline__ Roots stage_roots(sk::Cx<float>* lds, const sk::Cx<float>* tw, int S, int tid) {
+    sk::Cx<float>* hi = lds;
+    sk::Cx<float>* lo = lds + kRootHi;
+    const int nlo = S < kRootLo ? S : kRootLo;
+    const int nhi = S / nlo;
+    for (int e = tid; e < nhi; e += kBatchThreads) hi[e] = tw[e * kRootLo];
+    for (int e = tid; e < nlo; e += kBatchThreads) lo[e] = tw[e];
+    return Roots{hi, lo};
+}
+
+// In-place Stockham DFT stage of radix RAD on S = 2^lgS points in LDS (indexed through
+// padpos); kBatchThreads threads, up to 16 values each.
 template <int DIR, int RAD>
-__device__ __forceinline__ void lds_stage(sk::Cx<float>* buf, int S, int Ns,
-                                          const sk::Cx<float>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void lds_stage(sk::Cx<float>* buf, int S, int Ns, const Roots tw, int tid) {
     constexpr int NB = 16 / RAD;
     const int nb = S / RAD;
     const int stride = S / (Ns * RAD);
@@ -99,16 +121,19 @@ __device__ __forceinline__ void lds_stage(sk::Cx<float>* buf, int S, int Ns,
     __syncthreads();
 }
 
+// Radix-16 stages (one butterfly per thread at S = 16384), then one radix-2/4/8 stage.
 template <int DIR>
-__device__ void lds_dft(sk::Cx<float>* buf, int lgS, const sk::Cx<float>* __restrict__ tw, int tid) {
+__device__ void lds_dft(sk::Cx<float>* buf, int lgS, const Roots tw, int tid) {
     const int S = 1 << lgS;
     int Ns = 1, lg = lgS;
-    while (lg >= 2) {
-        lds_stage<DIR, 4>(buf, S, Ns, tw, tid);
-        Ns *= 4;
-        lg -= 2;
+    while (lg >= 4) {
+        lds_stage<DIR, 16>(buf, S, Ns, tw, tid);
+        Ns *= 16;
+        lg -= 4;
     }
-    if (lg == 1) lds_stage<DIR, 2>(buf, S, Ns, tw, tid);
+    if (lg == 3) lds_stage<DIR, 8>(buf, S, Ns, tw, tid);
+    else if (lg == 2) lds_stage<DIR, 4>(buf, S, Ns, tw, tid);
+    else if (lg == 1) lds_stage<DIR, 2>(buf, S, Ns, tw, tid);
 }
 
 __device__ __forceinline__ sk::Cx<float> mul_d(sk::Cx<float> v, double2 f) {
@@ -128,8 +153,35 @@ __device__ __forceinline__ sk::Cx<float> band_at(const InstDesc& d, const sk::Cx
     return mul_d(fhat[i], pre[i]);
 }
 
+// Element-wise pass over n items with U global loads in flight per thread: load(i) for U
+// items first, then store(i, value) for the same items.
+template <int U, typename T, typename Load, typename Store>
+__device__ __forceinline__ void staged_pass(int n, int tid, int nt, Load load, Store store) {
+    for (int base = tid; base < n; base += U * nt) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * nt;
+            if (i < n) v[u] = load(i);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * nt;
+            if (i < n) store(i, v[u]);
+        }
+    }
+}
+
+// Work item of the transform kernel: a whole instance (half < 0) or one of the two
+// half-length transforms of an instance with P = 2S (half = 0, 1).
+struct FftItem {
+    int inst;
+    int half;
+};
+
 struct FftArgs {
     const InstDesc* desc;
+    const FftItem* items;
     const void* fhat;
     void* theta;
     const double2* pre;
@@ -139,65 +191,146 @@ struct FftArgs {
     const void* tw;
 };
 
+// P = R S, pieces h = 0..R-1: X[R q + h] = DFT_S(y_h)[q] with
+// y_h[n] = e^{-2 pi i h n/P} sum_r b[n + r S] e^{-2 pi i r h/R}, and the inverse is
+// z[p] = sum_h e^{2 pi i h p/P} E_h[p mod S], E_h the inverse DFT of Z[R q + h] over q.
+// Each piece runs on its own workgroup and leaves E_h in scratch; k_batch_combine then
+// forms the outputs.
+// theta_l = u^{l^2} z[l mod P] with z[p] = sum_h e^{2 pi i h p/P} E_h[p mod S] (E_h in
+// scratch slices); all loads of an output are issued before its arithmetic.
+template <int R>
+__device__ __forceinline__ void combine_pieces(const InstDesc& d, const sk::Cx<float>* scr,
+                                               const sk::Cx<float>* twP, const double2* post,
+                                               sk::Cx<float>* theta, int tid, int NT) {
+    const int S = 1 << d.lgS;
+    for (int i = tid; i < d.L; i += NT) {
+        const int l = i - d.L / 2;
+        const int pz = l < 0 ? l + d.P : l;
+        const int n = pz & (S - 1);
+        sk::Cx<float> e[R], w[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            e[q] = scr[q * S + n];
+            w[q] = twP[(q * pz) & (d.P - 1)];
+        }
+        const double2 c = post[i];
+        sk::Cx<float> z{0.0f, 0.0f};
+#pragma unroll
+        for (int q = 0; q < R; ++q) z = sk::cadd(z, sk::cmul(e[q], w[q]));
+        theta[i] = mul_d(z, c);
+    }
+}
+
+// Radix-R decimation in frequency of the chirped band b (length P = R S): one thread per
+// position n < S computes y_h[n] = e^{-2 pi i h n/P} sum_r b[n + r S] e^{-2 pi i r h/R} for
+// every piece h and stores it to scratch slice h.
+struct DifItem {
+    int inst;
+    int n0;   // first position of this workgroup's 256
+};
+
+template <int R>
+__device__ __forceinline__ void dif_point(const InstDesc& d, const sk::Cx<float>* fhat, const double2* pre,
+                                          const sk::Cx<float>* twP, sk::Cx<float>* scr, int n) {
+    const int S = 1 << d.lgS;
+    sk::Cx<float> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = band_at(d, fhat, pre, n + r * S);
+    sk::dft<float, -1, R>(v);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        sk::Cx<float> w = twP[(q * n) & (d.P - 1)];
+        w.im = -w.im;
+        scr[q * S + n] = sk::cmul(v[sk::out_slot<R>(q)], w);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_batch_dif(FftArgs a, const DifItem* items) {
+    const DifItem it = items[blockIdx.x];
+    const InstDesc d = a.desc[it.inst];
+    const int n = it.n0 + int(threadIdx.x);
+    if (n >= (1 << d.lgS)) return;
+    const sk::Cx<float>* fhat = static_cast<const sk::Cx<float>*>(a.fhat) + d.fhat_off;
+    const double2* pre = a.pre + d.pre_off;
+    const sk::Cx<float>* twP = static_cast<const sk::Cx<float>*>(a.tw) + d.twP_off;
+    sk::Cx<float>* scr = static_cast<sk::Cx<float>*>(a.scratch) + d.scr_off;
+    switch (d.R) {
+        case 2: dif_point<2>(d, fhat, pre, twP, scr, n); break;
+        case 4: dif_point<4>(d, fhat, pre, twP, scr, n); break;
+        default: dif_point<8>(d, fhat, pre, twP, scr, n); break;
+    }
+}
+
 __global__ void __launch_bounds__(kBatchThreads) k_batch_fft(FftArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     sk::Cx<float>* buf = reinterpret_cast<sk::Cx<float>*>(smem_raw);
-    const InstDesc d = a.desc[blockIdx.x];
+    const FftItem item = a.items[blockIdx.x];
+    const InstDesc d = a.desc[item.inst];
     const int tid = threadIdx.x;
     const int S = 1 << d.lgS;
     const sk::Cx<float>* fhat = static_cast<const sk::Cx<float>*>(a.fhat) + d.fhat_off;
     const double2* pre = a.pre + d.pre_off;
     const double2* post = a.post + d.post_off;
     const sk::Cx<float>* H = static_cast<const sk::Cx<float>*>(a.h) + d.h_off;
-    const sk::Cx<float>* tw = static_cast<const sk::Cx<float>*>(a.tw) + d.tw_off;
     sk::Cx<float>* theta = static_cast<sk::Cx<float>*>(a.theta) + d.theta_off;
+    // root tables after the data buffer (visible to all threads after the first barrier)
+    const Roots tw = stage_roots(buf + (sk::padpos(kMaxLdsFft - 1) + 1),
+                                 static_cast<const sk::Cx<float>*>(a.tw) + d.tw_off, S, tid);
 
-    if (!d.split) {
-        for (int n = tid; n < S; n += kBatchThreads) buf[sk::padpos(n)] = band_at(d, fhat, pre, n);
+    using SCx = sk::Cx<float>;
+    constexpr int U = 8;
+    const int NT = kBatchThreads;
+    // output position i (centred l = i - L/2) reads cyclic position (l mod P)
+    auto out_pos = [&](int i) {
+        const int n = i - d.L / 2;
+        return n < 0 ? n + d.P : n;
+    };
+    auto mult_h = [&](int hoff, int hstride) {
+        staged_pass<U, SCx>(S, tid, NT, [&](int q) { return H[hstride * q + hoff]; },
+                            [&](int q, SCx hv) { buf[sk::padpos(q)] = sk::cmul(buf[sk::padpos(q)], hv); });
+    };
+    if (item.half < 0) {
+        staged_pass<U, SCx>(S, tid, NT, [&](int n) { return band_at(d, fhat, pre, n); },
+                            [&](int n, SCx v) { buf[sk::padpos(n)] = v; });
         __syncthreads();
         lds_dft<-1>(buf, d.lgS, tw, tid);
-        for (int q = tid; q < S; q += kBatchThreads) buf[sk::padpos(q)] = sk::cmul(buf[sk::padpos(q)], H[q]);
+        mult_h(0, 1);
         __syncthreads();
         lds_dft<+1>(buf, d.lgS, tw, tid);
-        for (int i = tid; i < d.L; i += kBatchThreads) {
-            int n = i - d.L / 2;
-            n += (n < 0) ? d.P : 0;
-            theta[i] = mul_d(buf[sk::padpos(n)], post[i]);
-        }
+        staged_pass<U, double2>(d.L, tid, NT, [&](int i) { return post[i]; },
+                                [&](int i, double2 c) { theta[i] = mul_d(buf[sk::padpos(out_pos(i))], c); });
         return;
     }
-    // P = 2S: X[2q + h] = DFT_S(y_h)[q] with y_0[n] = b[n] + b[n+S],
-    // y_1[n] = (b[n] - b[n+S]) e^{-2 pi i n/P}; the inverse is z[n] = E[n] + e^{2 pi i n/P} O[n]
-    // and z[n + S] = E[n] - e^{2 pi i n/P} O[n] with E, O the inverse DFTs of the halves.
+    const int h = item.half;
+    const int R = d.R;
     sk::Cx<float>* scr = static_cast<sk::Cx<float>*>(a.scratch) + d.scr_off;
     const sk::Cx<float>* twP = static_cast<const sk::Cx<float>*>(a.tw) + d.twP_off;
-    for (int n = tid; n < S; n += kBatchThreads) {
-        const sk::Cx<float> lo = band_at(d, fhat, pre, n), hi = band_at(d, fhat, pre, n + S);
-        sk::Cx<float> w = twP[n];
-        w.im = -w.im;
-        scr[n] = sk::cadd(lo, hi);
-        scr[S + n] = sk::cmul(sk::csub(lo, hi), w);
-    }
+    // y_h, written by k_batch_dif into this piece's slice of scratch
+    staged_pass<U, SCx>(S, tid, NT, [&](int n) { return scr[h * S + n]; },
+                        [&](int n, SCx v) { buf[sk::padpos(n)] = v; });
     __syncthreads();
-    for (int h = 0; h < 2; ++h) {
-        for (int n = tid; n < S; n += kBatchThreads) buf[sk::padpos(n)] = scr[h * S + n];
-        __syncthreads();
-        lds_dft<-1>(buf, d.lgS, tw, tid);
-        for (int q = tid; q < S; q += kBatchThreads)
-            buf[sk::padpos(q)] = sk::cmul(buf[sk::padpos(q)], H[2 * q + h]);
-        __syncthreads();
-        lds_dft<+1>(buf, d.lgS, tw, tid);
-        for (int n = tid; n < S; n += kBatchThreads) scr[h * S + n] = buf[sk::padpos(n)];
-        __syncthreads();
-    }
-    for (int i = tid; i < d.L; i += kBatchThreads) {
-        int n = i - d.L / 2;
-        n += (n < 0) ? d.P : 0;
-        const int nn = n < S ? n : n - S;
-        const sk::Cx<float> e = scr[nn], o = scr[S + nn];
-        const sk::Cx<float> wo = sk::cmul(o, twP[nn]);
-        const sk::Cx<float> z = n < S ? sk::cadd(e, wo) : sk::csub(e, wo);
-        theta[i] = mul_d(z, post[i]);
+    lds_dft<-1>(buf, d.lgS, tw, tid);
+    mult_h(h, R);
+    __syncthreads();
+    lds_dft<+1>(buf, d.lgS, tw, tid);
+    for (int n = tid; n < S; n += NT) scr[h * S + n] = buf[sk::padpos(n)];
+}
+
+// Output pass of instances split into R > 1 pieces (after every piece has run): one thread
+// per output, work items of 256 outputs.
+__global__ void __launch_bounds__(256) k_batch_combine(FftArgs a, const DifItem* items) {
+    const DifItem it = items[blockIdx.x];
+    const InstDesc d = a.desc[it.inst];
+    const int i = it.n0 + int(threadIdx.x);
+    if (i >= d.L) return;
+    const sk::Cx<float>* scr = static_cast<const sk::Cx<float>*>(a.scratch) + d.scr_off;
+    const sk::Cx<float>* twP = static_cast<const sk::Cx<float>*>(a.tw) + d.twP_off;
+    const double2* post = a.post + d.post_off;
+    sk::Cx<float>* theta = static_cast<sk::Cx<float>*>(a.theta) + d.theta_off;
+    switch (d.R) {
+        case 2: combine_pieces<2>(d, scr, twP, post, theta, i, d.L); break;
+        case 4: combine_pieces<4>(d, scr, twP, post, theta, i, d.L); break;
+        default: combine_pieces<8>(d, scr, twP, post, theta, i, d.L); break;
     }
 }
 
@@ -224,33 +357,90 @@ __device__ __forceinline__ int find_instance(const long long* off, int count, lo
     return lo;
 }
 
-__global__ void k_bbin_count(BBinArgs a) {
-    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.N) return;
+// Nodes of one workgroup are consecutive, so they fall into few tiles of one or two
+// instances: counts are aggregated in an LDS histogram over the workgroup's tile range
+// [tmin, tmin + kBinSpan) and flushed with one global atomic per tile; tiles beyond that
+// range (rare) use global atomics directly.
+constexpr int kBinThreads = 256;
+constexpr int kBinSpan = 512;
+
+__device__ __forceinline__ int block_min(int v, int* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = kBinThreads / 2; off > 0; off >>= 1) {
+        if (int(threadIdx.x) < off) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    const int r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int node_tile_of(const BBinArgs& a, long long j, unsigned& invalid, unsigned& outside) {
     const int i = find_instance(a.node_off, a.count, j);
     const InstDesc d = a.desc[i];
     float xv = a.x[j];
     if (!(xv >= -0.5f && xv < 0.5f)) {
-        atomicAdd(&a.flags[0], 1ull);
+        ++invalid;
         xv = 0.0f;
     }
     const float lim = 0.5f - float(d.m) / float(d.L);
-    if (!(xv >= -lim && xv < lim)) atomicAdd(&a.flags[1], 1ull);
+    if (!(xv >= -lim && xv < lim)) ++outside;
     int n;
     float th;
     dev::cell_of<float>(xv, d.L, n, th);
-    const int tile = d.tile_base + (n + d.L / 2) / a.tile;
-    a.node_tile[j] = tile;
-    atomicAdd(&a.tile_count[tile], 1);
+    return d.tile_base + (n + d.L / 2) / a.tile;
 }
 
-__global__ void k_bbin_scatter(const float* __restrict__ x, long long N, const int32_t* node_tile,
-                               const int32_t* offset, int32_t* cursor, int32_t* perm,
-                               float* __restrict__ xs) {
-    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kBinThreads) k_bbin_count(BBinArgs a) {
+    __shared__ int hist[kBinSpan];
+    __shared__ int red[kBinThreads];
+    __shared__ unsigned flag_cnt[2];
+    const long long j = (long long)blockIdx.x * kBinThreads + threadIdx.x;
+    for (int e = threadIdx.x; e < kBinSpan; e += kBinThreads) hist[e] = 0;
+    if (threadIdx.x < 2) flag_cnt[threadIdx.x] = 0u;
+    unsigned invalid = 0, outside = 0;
+    int tile = 0x7fffffff;
+    if (j < a.N) {
+        tile = node_tile_of(a, j, invalid, outside);
+        a.node_tile[j] = tile;
+    }
+    const int tmin = block_min(tile, red);   // also orders the LDS clears before use
+    if (j < a.N) {
+        const int k = tile - tmin;
+        if (k < kBinSpan) atomicAdd(&hist[k], 1);
+        else atomicAdd(&a.tile_count[tile], 1);
+    }
+    if (invalid) atomicAdd(&flag_cnt[0], invalid);
+    if (outside) atomicAdd(&flag_cnt[1], outside);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kBinSpan; e += kBinThreads)
+        if (hist[e]) atomicAdd(&a.tile_count[tmin + e], hist[e]);
+    if (threadIdx.x < 2 && flag_cnt[threadIdx.x])
+        atomicAdd(&a.flags[threadIdx.x], (unsigned long long)flag_cnt[threadIdx.x]);
+}
+
+// Each node takes its rank within the workgroup's share of its tile from the LDS
+// histogram; the workgroup reserves each tile's share with one global atomic.
+__global__ void __launch_bounds__(kBinThreads) k_bbin_scatter(const float* __restrict__ x, long long N,
+                                                             const int32_t* node_tile, const int32_t* offset,
+                                                             int32_t* cursor, int32_t* perm,
+                                                             float* __restrict__ xs) {
+    __shared__ int hist[kBinSpan];
+    __shared__ int red[kBinThreads];
+    const long long j = (long long)blockIdx.x * kBinThreads + threadIdx.x;
+    for (int e = threadIdx.x; e < kBinSpan; e += kBinThreads) hist[e] = 0;
+    const int tile = j < N ? node_tile[j] : 0x7fffffff;
+    const int tmin = block_min(tile, red);
+    int rank = -1;
+    if (j < N && tile - tmin < kBinSpan) rank = atomicAdd(&hist[tile - tmin], 1);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kBinSpan; e += kBinThreads)
+        if (hist[e]) hist[e] = atomicAdd(&cursor[tmin + e], hist[e]);
+    __syncthreads();
     if (j >= N) return;
-    const int tile = node_tile[j];
-    const int pos = offset[tile] + atomicAdd(&cursor[tile], 1);
+    const int pos = rank >= 0 ? offset[tile] + hist[tile - tmin] + rank
+                              : offset[tile] + atomicAdd(&cursor[tile], 1);
     perm[pos] = int32_t(j);
     xs[pos] = x[j];
 }
@@ -336,51 +526,58 @@ struct BGatherArgs {
     int tile;
 };
 
-template <int M2, int ACC>
-__device__ __forceinline__ void bgather_nodes(const BGatherArgs& a, const int4& ch, const InstDesc& d,
-                                              const CxF* lds, const float* coef, int n0) {
-    CxF* f = static_cast<CxF*>(a.f);
-    for (int jj = threadIdx.x; jj < ch.z; jj += blockDim.x) {
-        const long long j = (long long)ch.y + jj;
-        int n;
-        float theta[1];
-        dev::cell_of<float>(a.xs[j], d.L, n, theta[0]);
-        const int r = n + d.L / 2 - n0;
-        float w[1][M2];
-        dev::weights_poly<1, M2, kPolyCoef>(theta, coef, w);
-        typename std::conditional<ACC == 1, dev::WideAcc<float>, dev::Plain<float>>::type acc;
-#pragma unroll
-        for (int o = 0; o < M2; ++o) acc.add(w[0][o], lds[r + o]);
-        f[a.perm[j]] = acc.value();
-    }
+// Workgroups are dispatched round-robin over the 8 XCDs; map them so that consecutive
+// work-list entries (the same instance: its samples and its outputs) share one XCD's L2.
+__device__ __forceinline__ int xcd_block(int p, int n) {
+    constexpr int X = 8;
+    const int x = p % X;
+    const int q = n / X, r = n % X;
+    const int start = x * q + (x < r ? x : r);
+    return start + p / X;
 }
 
-template <int ACC>
-__global__ void __launch_bounds__(256) k_batch_gather(BGatherArgs a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int4 ch = a.chunks[blockIdx.x];
-    const InstDesc d = a.desc[ch.w];
+template <int M2, int ACC>
+__device__ __forceinline__ void batch_gather_chunk(const BGatherArgs& a, const int4 ch, const InstDesc& d,
+                                                   unsigned char* smem_raw) {
+    constexpr int m = M2 / 2;
     const int n0 = (ch.x - d.tile_base) * a.tile;
-    const int W = a.tile + 2 * d.m - 1;
+    const int W = a.tile + M2 - 1;
     CxF* lds = reinterpret_cast<CxF*>(smem_raw);
     float* coef = reinterpret_cast<float*>(smem_raw + ((size_t(a.tile + 2 * kMaxM) * sizeof(CxF) + 15) & ~size_t(15)));
     const CxF* th = static_cast<const CxF*>(a.theta) + d.theta_off;
-    for (int e = threadIdx.x; e < W; e += blockDim.x) {
-        const int p = n0 - d.m + 1 + e;
-        lds[e] = (p >= 0 && p < d.L) ? th[p] : CxF{0.0f, 0.0f};
-    }
-    for (int e = threadIdx.x; e < d.m * kPolyCoef; e += blockDim.x)
+    staged_pass<8, CxF>(W, int(threadIdx.x), int(blockDim.x),
+                        [&](int e) {
+                            const int p = n0 - m + 1 + e;
+                            return (p >= 0 && p < d.L) ? th[p] : CxF{0.0f, 0.0f};
+                        },
+                        [&](int e, CxF v) { lds[e] = v; });
+    for (int e = threadIdx.x; e < m * kPolyCoef; e += blockDim.x)
         coef[e] = a.coef[(long long)ch.w * kMaxM * kPolyCoef + e];
     __syncthreads();
-    switch (d.m) {
-        case 2: bgather_nodes<4, ACC>(a, ch, d, lds, coef, n0); break;
-        case 3: bgather_nodes<6, ACC>(a, ch, d, lds, coef, n0); break;
-        case 4: bgather_nodes<8, ACC>(a, ch, d, lds, coef, n0); break;
-        case 5: bgather_nodes<10, ACC>(a, ch, d, lds, coef, n0); break;
-        case 6: bgather_nodes<12, ACC>(a, ch, d, lds, coef, n0); break;
-        case 7: bgather_nodes<14, ACC>(a, ch, d, lds, coef, n0); break;
-        default: bgather_nodes<16, ACC>(a, ch, d, lds, coef, n0); break;
-    }
+    CxF* f = static_cast<CxF*>(a.f);
+    // node coordinates and output indices of up to 4 nodes per thread are loaded first
+    struct Node {
+        float x;
+        int32_t out;
+    };
+    staged_pass<4, Node>(ch.z, int(threadIdx.x), int(blockDim.x),
+                         [&](int jj) { return Node{a.xs[ch.y + jj], a.perm[ch.y + jj]}; },
+                         [&](int, Node nd) {
+                             int n;
+                             float theta[1];
+                             dev::cell_of<float>(nd.x, d.L, n, theta[0]);
+                             const int r = n + d.L / 2 - n0;
+                             float w[1][M2];
+                             // an opaque zero offset keeps the (uniform) coefficient loads
+                             // per node instead of holding all of them in registers
+                             int opaque = 0;
+                             asm volatile("" : "+s"(opaque));
+                             dev::weights_poly<1, M2, kPolyCoef>(theta, coef + opaque, w);
+                             typename std::conditional<ACC == 1, dev::WideAcc<float>, dev::Plain<float>>::type acc;
+#pragma unroll
+                             for (int o = 0; o < M2; ++o) acc.add(w[0][o], lds[r + o]);
+                             f[nd.out] = acc.value();
+                         });
 }
 
 __global__ void k_tile_scan_b(const int32_t* count, int32_t* offset, int32_t* chunk_off,
@@ -462,6 +659,7 @@ struct bl_batch_s {
     std::vector<bl::InstDesc> h_desc;
     std::vector<long long> h_node_off;
     std::vector<int32_t> h_tile_inst;
+    std::vector<bl::FftItem> h_items;    // transform work items, largest first
     int64_t total_M = 0, total_L = 0, total_N = 0;
     int tile = 512;
     int chunk_cap = 1024;
@@ -476,6 +674,11 @@ struct bl_batch_s {
     void* d_theta = nullptr;
     void* d_scratch = nullptr;
     float* d_coef = nullptr;
+    bl::FftItem* d_items = nullptr;
+    std::vector<bl::DifItem> h_dif;      // decimation work items (instances with R > 1)
+    bl::DifItem* d_dif = nullptr;
+    std::vector<bl::DifItem> h_comb;     // output items of instances with R > 1
+    bl::DifItem* d_comb = nullptr;
     // nodes
     float* d_xs = nullptr;
     int32_t* d_perm = nullptr;
@@ -521,29 +724,59 @@ bl_status balloc(T** p, size_t bytes) {
 }
 
 void free_batch(bl_batch_s* b) {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     void* ptrs[] = {b->d_desc, b->d_node_off, b->d_pre, b->d_post, b->d_h, b->d_tw, b->d_theta,
-                    b->d_scratch, b->d_coef, b->d_xs, b->d_perm, b->d_node_tile, b->d_tile_count,
+                    b->d_scratch, b->d_coef, b->d_items, b->d_dif, b->d_comb, b->d_xs, b->d_perm, b->d_node_tile, b->d_tile_count,
                     b->d_tile_offset, b->d_tile_cursor, b->d_chunk_offset, b->d_tile_inst,
                     b->d_chunks, b->d_flags};
-    for (void* q : ptrs) hipFree(q);
+    for (void* q : ptrs) (void)hipFree(q);
 }
 
 // Launch the transforms: one workgroup per instance, then the short sums.
+// One workgroup per work-list entry (a chunk of one instance's tile); the instance's m
+// selects the specialised body (uniform per workgroup).
+template <int ACC>
+__global__ void __launch_bounds__(256) k_batch_gather(BGatherArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int4 ch = a.chunks[xcd_block(int(blockIdx.x), int(gridDim.x))];
+    const InstDesc d = a.desc[ch.w];
+    switch (d.m) {
+        case 2: batch_gather_chunk<4, ACC>(a, ch, d, smem_raw); break;
+        case 3: batch_gather_chunk<6, ACC>(a, ch, d, smem_raw); break;
+        case 4: batch_gather_chunk<8, ACC>(a, ch, d, smem_raw); break;
+        case 5: batch_gather_chunk<10, ACC>(a, ch, d, smem_raw); break;
+        case 6: batch_gather_chunk<12, ACC>(a, ch, d, smem_raw); break;
+        case 7: batch_gather_chunk<14, ACC>(a, ch, d, smem_raw); break;
+        default: batch_gather_chunk<16, ACC>(a, ch, d, smem_raw); break;
+    }
+}
+
+// Launch the transforms (one workgroup per work item), then the short sums.
 bl_status batch_launches(bl_batch_s* b, hipStream_t s, const void* fhat, void* f, bool fft = true) {
     if (fft) {
-    FftArgs fa{};
-    fa.desc = b->d_desc;
-    fa.fhat = fhat;
-    fa.theta = b->d_theta;
-    fa.pre = b->d_pre;
-    fa.post = b->d_post;
-    fa.h = b->d_h;
-    fa.scratch = b->d_scratch;
-    fa.tw = b->d_tw;
-    hipLaunchKernelGGL(k_batch_fft, dim3(unsigned(b->count)), dim3(kBatchThreads), b->fft_lds, s, fa);
-    BL_HIP(hipGetLastError());
+        FftArgs fa{};
+        fa.desc = b->d_desc;
+        fa.items = b->d_items;
+        fa.fhat = fhat;
+        fa.theta = b->d_theta;
+        fa.pre = b->d_pre;
+        fa.post = b->d_post;
+        fa.h = b->d_h;
+        fa.scratch = b->d_scratch;
+        fa.tw = b->d_tw;
+        if (!b->h_dif.empty()) {
+            hipLaunchKernelGGL(k_batch_dif, dim3(unsigned(b->h_dif.size())), dim3(256), 0, s, fa,
+                               static_cast<const DifItem*>(b->d_dif));
+            BL_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_batch_fft, dim3(unsigned(b->h_items.size())), dim3(kBatchThreads), b->fft_lds, s, fa);
+        BL_HIP(hipGetLastError());
+        if (!b->h_comb.empty()) {
+            hipLaunchKernelGGL(k_batch_combine, dim3(unsigned(b->h_comb.size())), dim3(256), 0, s, fa,
+                               static_cast<const DifItem*>(b->d_comb));
+            BL_HIP(hipGetLastError());
+        }
     }
     if (b->nchunks == 0) return BL_OK;
     BGatherArgs ga{};
@@ -571,21 +804,26 @@ bl_status batch_bin(bl_batch_s* b, const float* x, int tile) {
     int64_t nt = 0;
     std::vector<int32_t>& tile_inst = b->h_tile_inst;
     tile_inst.clear();
-    for (int i = 0; i < b->count; ++i) {
-        b->h_desc[i].tile_base = int(nt);
-        b->h_desc[i].ntiles = int((b->h_desc[i].L + tile - 1) / tile);
-        nt += b->h_desc[i].ntiles;
-        for (int k = 0; k < b->h_desc[i].ntiles; ++k) tile_inst.push_back(i);
+    // Tiles are numbered instance by instance, grouped by m (neighbouring work-list entries
+    // then run the same specialised code).
+    for (int mm = 0; mm <= kMaxM; ++mm) {
+        for (int i = 0; i < b->count; ++i) {
+            if (b->h_desc[i].m != mm) continue;
+            b->h_desc[i].tile_base = int(nt);
+            b->h_desc[i].ntiles = int((b->h_desc[i].L + tile - 1) / tile);
+            nt += b->h_desc[i].ntiles;
+            for (int k = 0; k < b->h_desc[i].ntiles; ++k) tile_inst.push_back(i);
+        }
     }
     b->ntiles = nt;
     const int64_t N = b->total_N;
     const int64_t chunk_bound = N / b->chunk_cap + nt + 1;
     if (nt > b->tile_alloc) {
-        hipFree(b->d_tile_count);
-        hipFree(b->d_tile_offset);
-        hipFree(b->d_tile_cursor);
-        hipFree(b->d_chunk_offset);
-        hipFree(b->d_tile_inst);
+        (void)hipFree(b->d_tile_count);
+        (void)hipFree(b->d_tile_offset);
+        (void)hipFree(b->d_tile_cursor);
+        (void)hipFree(b->d_chunk_offset);
+        (void)hipFree(b->d_tile_inst);
         b->d_tile_count = b->d_tile_offset = b->d_tile_cursor = b->d_chunk_offset = b->d_tile_inst = nullptr;
         b->tile_alloc = 0;
         BL_TRY(balloc(&b->d_tile_count, sizeof(int32_t) * nt));
@@ -596,7 +834,7 @@ bl_status batch_bin(bl_batch_s* b, const float* x, int tile) {
         b->tile_alloc = nt;
     }
     if (chunk_bound > b->chunk_alloc) {
-        hipFree(b->d_chunks);
+        (void)hipFree(b->d_chunks);
         b->d_chunks = nullptr;
         b->chunk_alloc = 0;
         BL_TRY(balloc(&b->d_chunks, sizeof(int4) * chunk_bound));
@@ -620,14 +858,14 @@ bl_status batch_bin(bl_batch_s* b, const float* x, int tile) {
         ba.node_tile = b->d_node_tile;
         ba.tile_count = b->d_tile_count;
         ba.flags = b->d_flags;
-        hipLaunchKernelGGL(k_bbin_count, dim3(nb), dim3(256), 0, s, ba);
+        hipLaunchKernelGGL(k_bbin_count, dim3(nb), dim3(kBinThreads), 0, s, ba);
         BL_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_tile_scan_b, dim3(1), dim3(1024), 0, s, b->d_tile_count, b->d_tile_offset,
                        b->d_chunk_offset, (long long)nt, b->chunk_cap, b->d_flags);
     BL_HIP(hipGetLastError());
     if (N > 0) {
-        hipLaunchKernelGGL(k_bbin_scatter, dim3(nb), dim3(256), 0, s, x, (long long)N, b->d_node_tile,
+        hipLaunchKernelGGL(k_bbin_scatter, dim3(nb), dim3(kBinThreads), 0, s, x, (long long)N, b->d_node_tile,
                            b->d_tile_offset, b->d_tile_cursor, b->d_perm, b->d_xs);
         BL_HIP(hipGetLastError());
     }
@@ -665,9 +903,9 @@ bl_status autotune_tile(bl_batch_s* b, const float* x) {
         if (st != BL_OK) break;
         if ((st = batch_bin(b, x, cand)) != BL_OK) break;
         if ((st = batch_launches(b, b->stream, nullptr, fdummy, false)) != BL_OK) break;
-        hipEventRecord(e0, b->stream);
+        (void)hipEventRecord(e0, b->stream);
         for (int rep = 0; rep < 3 && st == BL_OK; ++rep) st = batch_launches(b, b->stream, nullptr, fdummy, false);
-        hipEventRecord(e1, b->stream);
+        (void)hipEventRecord(e1, b->stream);
         if (hipEventSynchronize(e1) != hipSuccess) st = bfail(BL_EDEVICE, "hipEventSynchronize failed");
         float ms = 0.0f;
         if (st == BL_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best) {
@@ -675,10 +913,10 @@ bl_status autotune_tile(bl_batch_s* b, const float* x) {
             best_tile = cand;
         }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    hipStreamSynchronize(b->stream);
-    hipFree(fdummy);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipFree(fdummy);
     if (st != BL_OK) return st;
     b->tile = best_tile;
     b->tuned = true;
@@ -687,8 +925,8 @@ bl_status autotune_tile(bl_batch_s* b, const float* x) {
 
 void drop_graph(bl_batch_s* b) {
     if (b->exec) {
-        hipStreamSynchronize(b->stream);   // a launch of the graph may still be in flight
-        hipGraphExecDestroy(b->exec);
+        (void)hipStreamSynchronize(b->stream);   // a launch of the graph may still be in flight
+        (void)hipGraphExecDestroy(b->exec);
     }
     b->exec = nullptr;
     b->g_fhat = nullptr;
@@ -758,7 +996,7 @@ bl_status bl_batch_create(bl_batch* out, int count, const int64_t* M, const int6
     int lds_fft_max = kMaxLdsFft;
     if (const char* e = std::getenv("BL_BATCH_LDS_FFT")) {
         const int v = std::atoi(e);
-        if (v >= 1024 && v <= kMaxLdsFft && (v & (v - 1)) == 0) lds_fft_max = v;
+        if (v >= 256 && v <= kMaxLdsFft && (v & (v - 1)) == 0) lds_fft_max = v;
     }
     long long node_off = 0;
     for (int i = 0; i < count; ++i) {
@@ -769,20 +1007,20 @@ bl_status bl_batch_create(bl_batch* out, int count, const int64_t* M, const int6
         int64_t P = 1;
         while (P < L[i] + M[i] - 1) P *= 2;
         d.P = int(P);
-        d.split = P > lds_fft_max ? 1 : 0;
-        if (P > 2 * int64_t(lds_fft_max))
-            return cleanup(bfail(BL_EUNSUPPORTED, "instance " + std::to_string(i) + ": transform above twice the LDS size"));
-        const int64_t S = d.split ? P / 2 : P;
+        const int64_t S = std::min<int64_t>(P, lds_fft_max);
+        d.R = int(P / S);
+        if (d.R > 8)
+            return cleanup(bfail(BL_EUNSUPPORTED, "instance " + std::to_string(i) + ": transform above eight LDS pieces"));
         d.lgS = ilog2i(S);
         d.tw_off = table(d.lgS);
-        d.twP_off = d.split ? table(ilog2i(P)) : 0;
+        d.twP_off = d.R > 1 ? table(ilog2i(P)) : 0;
         d.fhat_off = b->total_M;
         d.theta_off = b->total_L;
         d.pre_off = (long long)pre.size();
         d.post_off = (long long)post.size();
         d.h_off = (long long)(hbuf.size() / 2);
-        d.scr_off = d.split ? scr : 0;
-        if (d.split) scr += P;
+        d.scr_off = d.R > 1 ? scr : 0;
+        if (d.R > 1) scr += P;
         d.node_off = node_off;
         b->h_node_off[i] = node_off;
         node_off += N[i];
@@ -826,6 +1064,34 @@ bl_status bl_batch_create(bl_batch* out, int count, const int64_t* M, const int6
     b->h_node_off[count] = node_off;
     b->total_N = node_off;
     if (b->total_N > int64_t(0x7fffffff)) return cleanup(bfail(BL_EUNSUPPORTED, "total node count above 2^31"));
+    // Transform work items, most expensive first: whole instances (R = 1), or the R pieces
+    // of a larger one (each costs two DFTs of S points, R band loads per point and, for the
+    // last piece, the combination of the L outputs).
+    {
+        std::vector<std::pair<double, FftItem>> items;
+        for (int i = 0; i < count; ++i) {
+            const InstDesc& d = b->h_desc[i];
+            const double S = double(int64_t(1) << d.lgS);
+            const double cost = 2.0 * S * d.lgS + S * d.R + double(d.L) * d.R / 2.0;
+            if (d.R > 1) {
+                for (int h = 0; h < d.R; ++h) items.push_back({cost, FftItem{i, h}});
+            } else {
+                items.push_back({cost, FftItem{i, -1}});
+            }
+        }
+        std::stable_sort(items.begin(), items.end(),
+                         [](const std::pair<double, FftItem>& x, const std::pair<double, FftItem>& y) {
+                             return x.first > y.first;
+                         });
+        for (const auto& it : items) b->h_items.push_back(it.second);
+        for (int i = 0; i < count; ++i) {
+            const InstDesc& d = b->h_desc[i];
+            if (d.R > 1) {
+                for (int n0 = 0; n0 < (1 << d.lgS); n0 += 256) b->h_dif.push_back(DifItem{i, n0});
+                for (int i0 = 0; i0 < d.L; i0 += 256) b->h_comb.push_back(DifItem{i, i0});
+            }
+        }
+    }
 
     bl_status s;
     if ((s = balloc(&b->d_desc, sizeof(InstDesc) * count)) != BL_OK) return cleanup(s);
@@ -837,6 +1103,9 @@ bl_status bl_batch_create(bl_batch* out, int count, const int64_t* M, const int6
     if ((s = balloc(&b->d_theta, sizeof(CxF) * b->total_L)) != BL_OK) return cleanup(s);
     if ((s = balloc(&b->d_scratch, sizeof(CxF) * std::max<int64_t>(scr, 1))) != BL_OK) return cleanup(s);
     if ((s = balloc(&b->d_coef, sizeof(float) * coef.size())) != BL_OK) return cleanup(s);
+    if ((s = balloc(&b->d_items, sizeof(FftItem) * b->h_items.size())) != BL_OK) return cleanup(s);
+    if ((s = balloc(&b->d_comb, sizeof(DifItem) * b->h_comb.size())) != BL_OK) return cleanup(s);
+    if ((s = balloc(&b->d_dif, sizeof(DifItem) * b->h_dif.size())) != BL_OK) return cleanup(s);
     if ((s = balloc(&b->d_flags, sizeof(unsigned long long) * 4)) != BL_OK) return cleanup(s);
     const int64_t ncap = std::max<int64_t>(b->total_N, 1);
     if ((s = balloc(&b->d_xs, sizeof(float) * ncap)) != BL_OK) return cleanup(s);
@@ -851,13 +1120,19 @@ bl_status bl_batch_create(bl_batch* out, int count, const int64_t* M, const int6
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_h, hbuf.data(), sizeof(float) * hbuf.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_tw, tw.data(), sizeof(float) * tw.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_coef, coef.data(), sizeof(float) * coef.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_items, b->h_items.data(), sizeof(FftItem) * b->h_items.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !b->h_comb.empty())
+        e = hipMemcpyAsync(b->d_comb, b->h_comb.data(), sizeof(DifItem) * b->h_comb.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !b->h_dif.empty())
+        e = hipMemcpyAsync(b->d_dif, b->h_dif.data(), sizeof(DifItem) * b->h_dif.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(b->d_theta, 0, sizeof(CxF) * b->total_L, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return cleanup(bfail(BL_EDEVICE, std::string("table upload: ") + hipGetErrorString(e)));
 
     int lg_max = 0;
     for (const InstDesc& d : b->h_desc) lg_max = std::max(lg_max, d.lgS);
-    b->fft_lds = size_t(sk::padpos((1 << lg_max) - 1) + 1) * sizeof(CxF);
+    b->fft_lds = (size_t(sk::padpos(kMaxLdsFft - 1) + 1) + kRootHi + kRootLo) * sizeof(CxF);
+    (void)lg_max;
     if (b->fft_lds > 64 * 1024) {
         e = hipFuncSetAttribute((const void*)k_batch_fft, hipFuncAttributeMaxDynamicSharedMemorySize, int(b->fft_lds));
         if (e != hipSuccess) return cleanup(bfail(BL_EDEVICE, std::string("LDS attribute: ") + hipGetErrorString(e)));
@@ -897,13 +1172,13 @@ bl_status bl_batch_forward(bl_batch b, const void* fhat_dev, void* f_dev) {
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->capture_stream, &g);
         if (e != hipSuccess || e2 != hipSuccess || st != BL_OK) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             (void)hipGetLastError();
             if (st != BL_OK) return st;
             return bfail(BL_EDEVICE, "batched graph capture failed");
         }
         e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
             b->exec = nullptr;
             return bfail(BL_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
@@ -917,8 +1192,8 @@ bl_status bl_batch_forward(bl_batch b, const void* fhat_dev, void* f_dev) {
 
 bl_status bl_batch_destroy(bl_batch b) {
     if (!b) return BL_OK;
-    hipSetDevice(b->device);
-    hipStreamSynchronize(b->stream);
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
     free_batch(b);
     delete b;
     return BL_OK;

@@ -53,7 +53,7 @@ def _check(bp, insts, f, tol=TOL, sample=None, seed=0):
 
 
 # (M, L, m, N): power-of-two and other even L, the smallest M, an empty instance, the
-# largest in-LDS transform (L + M - 1 <= 16384) and the split one (L + M - 1 > 16384)
+# largest single-piece transform (L + M - 1 <= 4096) and ones split into 4 and 8 pieces
 MIXED = [(8, 16, 2, 50), (40, 60, 3, 300), (64, 128, 4, 1000), (100, 250, 5, 0),
          (256, 512, 6, 2000), (128, 160, 8, 700), (2, 6, 2, 10), (4000, 8000, 4, 1500),
          (8192, 16384, 8, 3000), (6000, 12000, 6, 2000), (1000, 1500, 7, 4000)]
@@ -63,6 +63,16 @@ MIXED = [(8, 16, 2, 50), (40, 60, 3, 300), (64, 128, 4, 1000), (100, 250, 5, 0),
 def test_batch_mixed_instances(precision):
     insts = _instances(MIXED, seed=41)
     bp, _, _, f = _run(insts, precision)
+    _check(bp, insts, f)
+
+
+def test_batch_small_pieces(monkeypatch):
+    """With the in-LDS transform size lowered to 256 points, instances split into 2, 4 and
+    8 pieces (and one that fits) on small sizes."""
+    monkeypatch.setenv("BL_BATCH_LDS_FFT", "256")
+    insts = _instances([(100, 250, 5, 700), (300, 600, 6, 900), (500, 1000, 4, 1100),
+                        (60, 120, 3, 300)], seed=48)
+    bp, _, _, f = _run(insts)
     _check(bp, insts, f)
 
 
