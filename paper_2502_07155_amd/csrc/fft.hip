@@ -71,6 +71,7 @@ __device__ __forceinline__ Cx<R> scale(Cx<R> v, double f) {
 // Global-memory view of one workgroup's B lines.
 template <typename TI, typename R, typename TO, int DIR, bool CONTIG>
 struct LineIO {
+    using In = TI;
     const Cx<TI>* __restrict__ in;
     Cx<TO>* __restrict__ out;
     const double* __restrict__ factor;
@@ -87,22 +88,33 @@ struct LineIO {
     // FFT input position pos of line b.  Forward: the band sample k with k - M/2 = pos
     // (mod L), times its factor; other positions are zero.  Adjoint: the centred sample
     // (pos + L/2) mod L.
-    __device__ __forceinline__ Cx<R> load(int b, int pos) const {
+    // Loads of FFT input position pos of line b, split from their use so that a thread's
+    // loads of one stage are all in flight together: fetch() issues the (predicated) loads
+    // of the value and, with FAC, of its factor; finish() forms the value.
+    template <bool FAC>
+    __device__ __forceinline__ bool fetch(int b, int pos, Cx<TI>& raw, double& fac) const {
         unsigned bi, bo;
-        if (!line(b, bi, bo)) return Cx<R>{R(0), R(0)};
+        bool ok = line(b, bi, bo);
         int k;
         if (DIR > 0) {
             k = pos + M / 2;
             if (k >= L) k -= L;
-            if (k >= Min) return Cx<R>{R(0), R(0)};
+            ok = ok && k < Min;
         } else {
             k = pos + L / 2;
             if (k >= L) k -= L;
         }
-        const Cx<TI> v = in[bi + unsigned(k) * unsigned(inner)];
-        Cx<R> r{R(v.re), R(v.im)};
-        if (DIR > 0 && factor) r = scale(r, factor[k]);
-        return r;
+        if (ok) {
+            raw = in[bi + unsigned(k) * unsigned(inner)];
+            if (DIR > 0 && FAC) fac = factor[k];
+        }
+        return ok;
+    }
+    template <bool FAC>
+    __device__ __forceinline__ Cx<R> finish(bool ok, Cx<TI> raw, double fac) const {
+        if (!ok) return Cx<R>{R(0), R(0)};
+        const Cx<R> r{R(raw.re), R(raw.im)};
+        return (DIR > 0 && FAC) ? scale(r, fac) : r;
     }
     // FFT output position q of line b.  Forward: centred index (q + L/2) mod L.  Adjoint:
     // the band entry k with k - M/2 = q (mod L), times its factor; other q are dropped.
@@ -129,22 +141,35 @@ struct LineIO {
 // k = j mod Ns, w = e^{dir 2 pi i/(Ns RAD)} (tw holds this stage's w^{r k} at
 // k (RAD-1) + r - 1), and writes positions (j - k) RAD + k + r Ns.
 // SRC/DST: 0 = LDS, 1 = global (the first stage reads HBM, the last writes HBM).
-template <typename R, int E, int RAD, bool CONTIG, int SRC, typename IO>
+template <typename R, int E, int RAD, bool CONTIG, int SRC, typename IO, bool FAC = false>
 __device__ __forceinline__ void stage_read(Cx<R>* reg, const Cx<R>* lds, const IO& io, int lgL,
                                            int lgB, int Lp, int tid, int NT) {
     constexpr int NB = E / RAD;
     constexpr int lgR = RAD == 2 ? 1 : RAD == 4 ? 2 : RAD == 8 ? 3 : 4;
     const int lgLR = lgL - lgR;
     const int LR = 1 << lgLR;
+    if constexpr (SRC == 0) {
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        int b, j;
-        map_butterfly<CONTIG>(tid + u * NT, lgB, lgLR, b, j);
+        for (int u = 0; u < NB; ++u) {
+            int b, j;
+            map_butterfly<CONTIG>(tid + u * NT, lgB, lgLR, b, j);
 #pragma unroll
-        for (int r = 0; r < RAD; ++r) {
-            const int pos = j + r * LR;
-            reg[u * RAD + r] = SRC == 0 ? lds[lds_index<CONTIG>(b, pos, lgB, Lp)] : io.load(b, pos);
+            for (int r = 0; r < RAD; ++r) reg[u * RAD + r] = lds[lds_index<CONTIG>(b, j + r * LR, lgB, Lp)];
         }
+    } else {
+        Cx<typename IO::In> raw[NB * RAD];
+        double fac[NB * RAD];
+        bool ok[NB * RAD];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            int b, j;
+            map_butterfly<CONTIG>(tid + u * NT, lgB, lgLR, b, j);
+#pragma unroll
+            for (int r = 0; r < RAD; ++r)
+                ok[u * RAD + r] = io.template fetch<FAC>(b, j + r * LR, raw[u * RAD + r], fac[u * RAD + r]);
+        }
+#pragma unroll
+        for (int q = 0; q < NB * RAD; ++q) reg[q] = io.template finish<FAC>(ok[q], raw[q], fac[q]);
     }
 }
 
@@ -239,10 +264,18 @@ __global__ void __launch_bounds__(max_threads<R>()) k_fft_pass(PassArgs a) {
     // First stage: radix E, Ns = 1 (no twiddles).  Its HBM reads are issued before the
     // twiddle table is staged, so the two latencies overlap.
     Cx<R> reg[E];
-    stage_read<R, E, E, CONTIG, 1>(reg, lds, io, a.lgL, a.lgB, Lp, tid, NT);
+    if (a.factor) stage_read<R, E, E, CONTIG, 1, decltype(io), true>(reg, lds, io, a.lgL, a.lgB, Lp, tid, NT);
+    else stage_read<R, E, E, CONTIG, 1, decltype(io), false>(reg, lds, io, a.lgL, a.lgB, Lp, tid, NT);
     if (a.tw_in_lds) {
         Cx<R>* twl = lds + size_t(B) * Lp;
-        for (int e = tid; e < a.tw_len; e += NT) twl[e] = tw[e];
+        for (int e0 = tid; e0 < a.tw_len; e0 += 4 * NT) {
+            Cx<R> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = tw[min(e0 + u * NT, a.tw_len - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e0 + u * NT < a.tw_len) twl[e0 + u * NT] = v[u];
+        }
         tw = twl;
     }
     const int nstages = a.nmain + (a.rlast > 1 ? 1 : 0);
