@@ -96,10 +96,19 @@ void free_plan(Plan& p) {
 
 // Tile edge per dimension for the short-sum kernels: the staged tile plus halo must fit
 // the LDS budget.
+// Tile edge per dimension: the default edge, shrunk until the staged box (stored twice for
+// float tiles with d >= 2) fits the LDS budget.  The d = 3 budget keeps at least three
+// workgroups per CU (measured: occupancy outweighs the larger halo overhead there).
 void choose_tiles(Plan& p) {
     const int d = p.d;
-    const size_t c = p.cplx_size();
-    const size_t budget = 64 * 1024;
+    const size_t budget = (d == 3 ? 44 : 64) * 1024;
+    auto box = [&](int t) {
+        size_t e = 1;
+        for (int k = 0; k < d; ++k) e *= size_t(t + 2 * p.m - 1);
+        return e;
+    };
+    p.dual_tiles = dual_tiles_for(d, p.m, p.prec != BL_F64);
+    const size_t c = p.cplx_size() * (p.dual_tiles ? 2 : 1);
     int T;
     if (d == 1) T = 512;
     else if (d == 2) T = 16;
@@ -108,12 +117,7 @@ void choose_tiles(Plan& p) {
         const int v = std::atoi(e);
         if (v >= 1 && v <= 4096) T = v;
     }
-    auto bytes = [&](int t) {
-        size_t e = 1;
-        for (int k = 0; k < d; ++k) e *= size_t(t + 2 * p.m - 1);
-        return e * c;
-    };
-    while (T > 1 && bytes(T) > budget) T /= 2;
+    while (T > 1 && box(T) * c > budget) --T;
     if (T > p.L) T = int(p.L);
     p.ntiles = 1;
     for (int t = 0; t < 3; ++t) {

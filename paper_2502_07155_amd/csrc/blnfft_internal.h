@@ -36,6 +36,11 @@ constexpr int kMinM = 2;    // truncation range of the compiled short-sum kernel
 constexpr int kMaxM = 8;
 constexpr int kPolyCoef = 12;   // coefficients of the float weight polynomials (degree 11)
 constexpr int kPolyCoef64 = 16; // coefficients of the double weight polynomials (degree 15)
+// Float tiles of the short sums are staged twice (shifted copies, for 128-bit row reads)
+// when the doubled tile still leaves room for several workgroups per CU.
+constexpr bool dual_tiles_for(int d, int m, bool is_float) {
+    return is_float && (d == 2 || (d == 3 && m <= 5));
+}
 
 // Factorisation of one FFT length into Stockham stages.
 struct FftFactors {
@@ -110,6 +115,8 @@ struct Plan {
     int tiles_per_dim[3] = {1, 1, 1};
     int64_t ntiles = 0;
     int chunk_cap = 1024;
+    // float tiles of d >= 2 staged twice (shifted copies) for 128-bit row reads
+    bool dual_tiles = false;
     int32_t* d_tile_count = nullptr;
     int32_t* d_tile_offset = nullptr;
     int32_t* d_tile_cursor = nullptr;

@@ -250,12 +250,12 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
     int S[3] = {1, 1, 1};
     if (D >= 2) S[D - 2] = a.pitch[D - 1];
     if (D >= 3) S[0] = S[1] * W[1];
-    // d = 2 float tiles are stored twice, the second copy shifted by one element, so that
-    // every node's rows start 16-byte aligned in one of them and are read with 128-bit
-    // loads (the row pitch is even).
-    constexpr bool kDual = D == 2 && std::is_same<R, float>::value;
-    const int one_copy = kDual ? ((S[0] * W[0] + 1) & ~1) : S[0] * W[0];
-    const int lds_elems = kDual ? 2 * one_copy : one_copy;
+    // d = 2, 3 float tiles are stored twice, the second copy shifted by one element, so
+    // that every node's rows start 16-byte aligned in one of them and are read with
+    // 128-bit loads (the row pitch is even).
+    constexpr bool dual = dual_tiles_for(D, M2 / 2, std::is_same<R, float>::value);
+    const int one_copy = dual ? ((S[0] * W[0] + 1) & ~1) : S[0] * W[0];
+    const int lds_elems = dual ? 2 * one_copy : one_copy;
     Cx<R>* ldsB = lds + one_copy;
     const Cx<R>* __restrict__ th = static_cast<const Cx<R>*>(a.theta);
     // float weight polynomials after the tile in LDS, 16-byte aligned
@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
         for (int u = 0; u < kStage; ++u) {
             if (lis[u] < 0) continue;
             lds[lis[u]] = v[u];
-            if (kDual && lis[u] > 0) ldsB[lis[u] - 1] = v[u];
+            if (dual && lis[u] > 0) ldsB[lis[u] - 1] = v[u];
         }
     }
     __syncthreads();
@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
         } else if constexpr (D == 2) {
             const int base = r[0] * S[0] + r[1];
             Outer acc;
-            if constexpr (kDual) {
+            if constexpr (dual) {
                 const Cx<R>* src = (base & 1) ? ldsB + (base - 1) : lds + base;
 #pragma unroll
                 for (int o0 = 0; o0 < M2; ++o0) {
@@ -402,10 +402,21 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
                 Plain<R> pacc;
 #pragma unroll
                 for (int o1 = 0; o1 < M2; ++o1) {
-                    const Cx<R>* row = lds + base + o0 * S[0] + o1 * S[1];
                     Plain<R> racc;
+                    if constexpr (dual) {
+                        const Cx<R>* src = (base & 1) ? ldsB + (base - 1) : lds + base;
+                        const float4* row = reinterpret_cast<const float4*>(src + o0 * S[0] + o1 * S[1]);
 #pragma unroll
-                    for (int o2 = 0; o2 < M2; ++o2) racc.add(w[2][o2], row[o2]);
+                        for (int q = 0; q < M2 / 2; ++q) {
+                            const float4 v = row[q];
+                            racc.add(w[2][2 * q], Cx<R>{v.x, v.y});
+                            racc.add(w[2][2 * q + 1], Cx<R>{v.z, v.w});
+                        }
+                    } else {
+                        const Cx<R>* row = lds + base + o0 * S[0] + o1 * S[1];
+#pragma unroll
+                        for (int o2 = 0; o2 < M2; ++o2) racc.add(w[2][o2], row[o2]);
+                    }
                     pacc.add(w[1][o1], racc.value());
                 }
                 acc.add(w0, pacc.value());
@@ -464,7 +475,7 @@ dev::WinF32 make_win_f32(const Plan& p) {
 // LDS pitch (elements) of the staged tile's innermost row.  Rows are padded so that a
 // row step moves by half of the 64 LDS banks: lanes reading neighbouring tile rows then
 // fall on disjoint banks.
-bool dual_tile(const Plan& p) { return p.d == 2 && p.prec != BL_F64; }
+bool dual_tile(const Plan& p) { return p.dual_tiles; }
 
 int tile_pitch(const Plan& p) {
     const int w = p.tile[p.d - 1] + 2 * p.m - 1;
