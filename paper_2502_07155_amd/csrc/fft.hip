@@ -225,13 +225,15 @@ __device__ __forceinline__ int xcd_block(int p, int n) {
     return start + p / X;
 }
 
-template <typename R>
-constexpr int max_threads() { return 512; }
+// Threads per workgroup: 1024 with four values per thread, 512 with sixteen (register
+// pressure of the radix-16 butterflies in double).
+template <int E>
+constexpr int max_threads() { return E == 4 ? 1024 : 512; }
 
 // TI: input element type, R: LDS / arithmetic type, TO: output element type, E: values per
 // thread (= the main radix: 16, or 4 when the pass has few lines and needs more threads).
 template <typename TI, typename R, typename TO, int DIR, bool CONTIG, int E>
-__global__ void __launch_bounds__(max_threads<R>()) k_fft_pass(PassArgs a) {
+__global__ void __launch_bounds__(max_threads<E>()) k_fft_pass(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x;
     const int NT = blockDim.x;
@@ -315,14 +317,12 @@ int ilog2(int v) {
     return l;
 }
 
-// Lines per workgroup: enough to coalesce strided accesses, threads B*L/E <= 1024, and
-// LDS within `lds_cap` bytes.
-// Lines per workgroup: enough to coalesce strided accesses, threads B*L/E <= 512, and
-// LDS within 96 KB.
+// Lines per workgroup: enough to coalesce strided accesses, threads B*L/E within
+// max_threads, and LDS within 96 KB.
 int choose_lines(const Plan& p, size_t c, int E) {
     const int L = int(p.L);
     const int bmax = (c == 16) ? 8 : 16;
-    const int tmax = 512;
+    const int tmax = E == 4 ? 1024 : 512;
     int b = 1;
     while (b * 2 <= bmax && (int64_t(b) * 2 * L) / E <= tmax &&
            size_t(b) * 2 * size_t(padpos(L - 1) + 1) * c <= 96 * 1024)
@@ -365,7 +365,7 @@ bl_status run_pass_e(Plan& p, PassArgs a) {
     const size_t twb = size_t(a.tw_len) * sizeof(Cx<R>);
     a.tw_in_lds = (twb <= 32 * 1024 && data + twb <= 160 * 1024) ? 1 : 0;
     const size_t lds = data + (a.tw_in_lds ? twb : 0);
-    if (NT > max_threads<R>() || lds > 160 * 1024) {
+    if (NT > max_threads<E>() || lds > 160 * 1024) {
         set_error("FFT length too large for the LDS pass kernel");
         return BL_EUNSUPPORTED;
     }
