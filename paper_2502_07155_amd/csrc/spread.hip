@@ -10,6 +10,8 @@
 //
 // The gradient kernel mirrors the short-sum kernel, with psi' in one dimension:
 //   d f_j / d x_jt = L sum_l theta_l psi_g'(u_t) prod_{s != t} psi_g(u_s).
+#include <cstdlib>
+
 #include "blnfft_internal.h"
 #include "device_math.h"
 
@@ -168,6 +170,179 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
     }
 }
 
+// Output-stationary spreading (LDS float atomics are slow on this GPU): each thread owns
+// grid points of the chunk's box (tile plus halo) and accumulates, in registers, the
+// contributions of the nodes whose window covers them.  The chunk's nodes are processed in
+// batches of kOsBatch: their cells, weights and values go to LDS, then for a grid point the
+// contributing nodes of each tile row in reach form a contiguous range of the cell-sorted
+// batch (found from a per-cell start table), so no node outside the window is visited.
+// The box is finally added to the grid with hardware float atomics (boxes overlap).
+constexpr int kOsThreads = 256;
+constexpr int kOsBatch = 256;
+template <int D>
+constexpr int os_points() { return D == 1 ? 4 : D == 2 ? 8 : 20; }   // box points per thread
+
+template <typename R, int D, int M2, int METHOD>
+__global__ void __launch_bounds__(kOsThreads) k_spread_os(SpreadArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int m = M2 / 2;
+    constexpr int KP = os_points<D>();
+    const int4 ch = a.chunks[blockIdx.x];
+    const int L = a.L;
+    const int tid = threadIdx.x;
+    int n0[3] = {0, 0, 0}, W[3] = {1, 1, 1}, T[3] = {1, 1, 1};
+    tile_geometry<D>(ch, a.tpd, a.tile, M2, n0, W);
+#pragma unroll
+    for (int t = 0; t < D; ++t) T[t] = a.tile[t];
+    const int total = W[0] * W[1] * W[2];
+    const int ncell = T[0] * T[1] * T[2];
+    // LDS: weights [D][M2][kOsBatch], values [kOsBatch], cells [kOsBatch], starts [ncell+1], coef
+    R* wts = reinterpret_cast<R*>(smem_raw);
+    Cx<R>* gv = reinterpret_cast<Cx<R>*>(wts + D * M2 * kOsBatch);
+    int* key = reinterpret_cast<int*>(gv + kOsBatch);
+    int* start = key + kOsBatch;
+    float* coef = reinterpret_cast<float*>(smem_raw + ((size_t(reinterpret_cast<unsigned char*>(start + ncell + 1) - smem_raw) + 15) & ~size_t(15)));
+    if constexpr (std::is_same<R, float>::value) {
+        for (int e = tid; e < m * kPolyCoef; e += kOsThreads) coef[e] = a.poly[e];
+    }
+    Cx<R> acc[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) acc[k] = Cx<R>{R(0), R(0)};
+
+    const R* __restrict__ xs = static_cast<const R*>(a.xs);
+    const Cx<R>* __restrict__ g = static_cast<const Cx<R>*>(a.g);
+    const R beta = R(a.beta), cb = R(a.cb), inv_m2 = R(1) / R(m * m);
+    for (int b0 = 0; b0 < ch.z; b0 += kOsBatch) {
+        const int nb = min(kOsBatch, ch.z - b0);
+        __syncthreads();   // coefficients staged / previous batch consumed
+        if (tid < nb) {
+            const int64_t j = int64_t(ch.y) + b0 + tid;
+            R theta[D];
+            int kc = 0;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                int nc;
+                cell_of<R>(xs[j * D + t], L, nc, theta[t]);
+                kc = kc * T[t] + (nc + L / 2 - n0[t]);
+            }
+            R w[D][M2];
+            if constexpr (std::is_same<R, float>::value) {
+                weights_poly<D, M2, kPolyCoef>(theta, coef, w);
+            } else {
+#pragma unroll
+                for (int t = 0; t < D; ++t) weights<R, M2, METHOD>(theta[t], beta, cb, inv_m2, w[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+#pragma unroll
+                for (int o = 0; o < M2; ++o) wts[(t * M2 + o) * kOsBatch + tid] = w[t][o];
+            gv[tid] = g[a.perm[j]];
+            key[tid] = kc;
+        }
+        __syncthreads();
+        // start[c] = first batch position with cell >= c (the batch is sorted by cell)
+        for (int c = tid; c <= ncell; c += kOsThreads) {
+            int lo = 0, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key[mid] < c) lo = mid + 1;
+                else hi = mid;
+            }
+            start[c] = lo;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int e = tid + k * kOsThreads;
+            if (e >= total) break;
+            int c[3] = {0, 0, 0};
+            {
+                int rem = e;
+#pragma unroll
+                for (int t = D - 1; t >= 0; --t) {
+                    c[t] = rem % W[t];
+                    rem /= W[t];
+                }
+            }
+            // tile cells in reach of box point c along t: r in [c - M2 + 1, c] within [0, T)
+            int lo[3], hi[3];
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                lo[t] = max(0, c[t] - M2 + 1);
+                hi[t] = min(T[t] - 1, c[t]);
+            }
+            Cx<R> sum = acc[k];
+            auto visit = [&](int rowkey, int wprod_off0, R wpre) {
+                // contiguous cells rowkey + lo..hi along the last dimension
+                const int jb = start[rowkey + lo[D - 1]], je = start[rowkey + hi[D - 1] + 1];
+                for (int j = jb; j < je; ++j) {
+                    const int rl = key[j] - rowkey;   // cell along the last dimension
+                    const R wl = wts[((D - 1) * M2 + (c[D - 1] - rl)) * kOsBatch + j];
+                    R wv = wl * wpre;
+                    if (wprod_off0 >= 0) wv *= wts[wprod_off0 + j];
+                    const Cx<R> gj = gv[j];
+                    sum.re = dev_fma(wv, gj.re, sum.re);
+                    sum.im = dev_fma(wv, gj.im, sum.im);
+                }
+            };
+            if constexpr (D == 1) {
+                if (lo[0] <= hi[0]) visit(0, -1, R(1));
+            } else if constexpr (D == 2) {
+                if (lo[1] <= hi[1])
+                    for (int r0 = lo[0]; r0 <= hi[0]; ++r0)
+                        visit(r0 * T[1], (0 * M2 + (c[0] - r0)) * kOsBatch, R(1));
+            } else {
+                if (lo[2] <= hi[2])
+                    for (int r0 = lo[0]; r0 <= hi[0]; ++r0)
+                        for (int r1 = lo[1]; r1 <= hi[1]; ++r1) {
+                            // the node's w0 and w1 both vary per node: w0 folded in per node
+                            const int rowkey = (r0 * T[1] + r1) * T[2];
+                            const int jb = start[rowkey + lo[2]], je = start[rowkey + hi[2] + 1];
+                            const int off0 = (0 * M2 + (c[0] - r0)) * kOsBatch;
+                            const int off1 = (1 * M2 + (c[1] - r1)) * kOsBatch;
+                            for (int j = jb; j < je; ++j) {
+                                const int r2 = key[j] - rowkey;
+                                const R wv = wts[off0 + j] * wts[off1 + j] *
+                                             wts[(2 * M2 + (c[2] - r2)) * kOsBatch + j];
+                                const Cx<R> gj = gv[j];
+                                sum.re = dev_fma(wv, gj.re, sum.re);
+                                sum.im = dev_fma(wv, gj.im, sum.im);
+                            }
+                        }
+            }
+            acc[k] = sum;
+        }
+    }
+
+    R* __restrict__ grid = static_cast<R*>(a.grid);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int e = tid + k * kOsThreads;
+        if (e >= total) break;
+        if (acc[k].re == R(0) && acc[k].im == R(0)) continue;
+        int rem = e;
+        int64_t gidx = 0;
+        bool ok = true;
+        int64_t st = 1;
+#pragma unroll
+        for (int t = D - 1; t >= 0; --t) {
+            const int ct = rem % W[t];
+            rem /= W[t];
+            int p = n0[t] - m + 1 + ct;
+            if (METHOD == 1) {
+                p = (p % L + L) % L;
+            } else if (p < 0 || p >= L) {
+                ok = false;
+            }
+            gidx += int64_t(p) * st;
+            st *= L;
+        }
+        if (!ok) continue;
+        hbm_add(grid + 2 * gidx, acc[k].re);
+        hbm_add(grid + 2 * gidx + 1, acc[k].im);
+    }
+}
+
 template <typename R, int D, int M2>
 __global__ void __launch_bounds__(256) k_grad_x(SpreadArgs a) {
     extern __shared__ unsigned char smem_raw[];
@@ -302,6 +477,28 @@ KFn grad_m(int m) {
     }
 }
 
+template <typename R, int D, int METHOD>
+KFn spread_os_m(int m) {
+    switch (m) {
+        case 2: return k_spread_os<R, D, 4, METHOD>;
+        case 3: return k_spread_os<R, D, 6, METHOD>;
+        case 4: return k_spread_os<R, D, 8, METHOD>;
+        case 5: return k_spread_os<R, D, 10, METHOD>;
+        case 6: return k_spread_os<R, D, 12, METHOD>;
+        case 7: return k_spread_os<R, D, 14, METHOD>;
+        case 8: return k_spread_os<R, D, 16, METHOD>;
+        default: return nullptr;
+    }
+}
+
+template <typename R, int METHOD>
+KFn spread_os_d(int d, int m) {
+    if (d == 1) return spread_os_m<R, 1, METHOD>(m);
+    if (d == 2) return spread_os_m<R, 2, METHOD>(m);
+    if (d == 3) return spread_os_m<R, 3, METHOD>(m);
+    return nullptr;
+}
+
 template <typename R, int METHOD>
 KFn spread_d(int d, int m) {
     if (d == 1) return spread_m<R, 1, METHOD>(m);
@@ -346,17 +543,35 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
         hipLaunchKernelGGL(k_zero<float>, dim3(zb), dim3(256), 0, p.stream, static_cast<Cx<float>*>(grid), n);
     BL_HIP(hipGetLastError());
     if (p.N == 0 || p.nchunks == 0) return BL_OK;
+    SpreadArgs a = make_args(p);
+    a.g = g;
+    a.grid = grid;
+    // Output-stationary kernel when the box fits its points per thread and its LDS fits;
+    // otherwise the LDS-atomic kernel.
+    int64_t box = 1, ncell = 1;
+    for (int t = 0; t < p.d; ++t) {
+        box *= p.tile[t] + 2 * p.m - 1;
+        ncell *= p.tile[t];
+    }
+    const int kp = p.d == 1 ? os_points<1>() : p.d == 2 ? os_points<2>() : os_points<3>();
+    const size_t rs = p.prec == BL_F64 ? 8 : 4;
+    const size_t os_lds = ((rs * p.d * 2 * p.m * kOsBatch + 2 * rs * kOsBatch + 4 * kOsBatch +
+                            4 * size_t(ncell + 1) + 15) & ~size_t(15)) + sizeof(float) * kMaxM * kPolyCoef;
+    const bool use_os = box <= int64_t(kp) * kOsThreads && os_lds <= 64 * 1024 &&
+                        std::getenv("BL_SPREAD_ATOMIC") == nullptr;
     KFn fn;
-    if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_d<double, 1>(p.d, p.m) : spread_d<double, 0>(p.d, p.m);
-    else fn = p.method == BL_NFFT ? spread_d<float, 1>(p.d, p.m) : spread_d<float, 0>(p.d, p.m);
+    if (use_os) {
+        if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_os_d<double, 1>(p.d, p.m) : spread_os_d<double, 0>(p.d, p.m);
+        else fn = p.method == BL_NFFT ? spread_os_d<float, 1>(p.d, p.m) : spread_os_d<float, 0>(p.d, p.m);
+    } else {
+        if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_d<double, 1>(p.d, p.m) : spread_d<double, 0>(p.d, p.m);
+        else fn = p.method == BL_NFFT ? spread_d<float, 1>(p.d, p.m) : spread_d<float, 0>(p.d, p.m);
+    }
     if (!fn) {
         set_error("no spreading kernel for this (d, m)");
         return BL_EUNSUPPORTED;
     }
-    SpreadArgs a = make_args(p);
-    a.g = g;
-    a.grid = grid;
-    const size_t lds = box_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
+    const size_t lds = use_os ? os_lds : box_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);
