@@ -343,6 +343,154 @@ __global__ void __launch_bounds__(kOsThreads) k_spread_os(SpreadArgs a) {
     }
 }
 
+// d = 2 spreading by tile rows.  Lane l of wave w owns the box column c1 = l mod 32 and
+// the four box rows c0 = 8w + 4 (l div 32) + k, k < 4, so a box of at most 32 x 32 points
+// is covered by 256 threads.  For a batch of the chunk's nodes, LDS holds both dimensions'
+// weights of every node at their absolute box coordinates (zero elsewhere): a lane reads
+// the weight of any node at its own row and column without knowing the node's cell, and
+// a wave walks its nodes in groups of 16 bytes per load (the node values and first-
+// dimension weights are broadcast reads).  A wave visits only the nodes of the tile rows
+// that reach its eight box rows; others contribute zero and are harmless at group ends.
+template <typename R>
+constexpr int rows_batch() { return std::is_same<R, float>::value ? 128 : 64; }
+template <typename R>
+constexpr int rows_pitch() { return rows_batch<R>() + 16 / int(sizeof(R)); }   // spreads the banks
+template <typename R>
+constexpr size_t rows_lds_bytes() {
+    return sizeof(R) * 64 * rows_pitch<R>() + sizeof(Cx<R>) * rows_batch<R>() +
+           sizeof(int) * (48 + rows_batch<R>()) + sizeof(float) * kMaxM * kPolyCoef;
+}
+
+template <typename R, int M2, int METHOD>
+__global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int m = M2 / 2;
+    constexpr int NB = rows_batch<R>();
+    constexpr int P = rows_pitch<R>();
+    constexpr int VEC = 16 / int(sizeof(R));   // nodes per 16-byte load
+    typedef R vec_t __attribute__((ext_vector_type(VEC)));
+    R* w0s = reinterpret_cast<R*>(smem_raw);     // [32][P]: first-dimension weight at box row
+    R* w1s = w0s + 32 * P;                       // [32][P]: last-dimension weight at box column
+    Cx<R>* gv = reinterpret_cast<Cx<R>*>(w1s + 32 * P);   // [NB]
+    int* rowstart = reinterpret_cast<int*>(gv + NB);      // [T0 + 1], T0 <= 32
+    int* key = rowstart + 48;                             // [NB]
+    float* coef = reinterpret_cast<float*>(key + NB);
+
+    const int4 ch = a.chunks[blockIdx.x];
+    const int L = a.L;
+    const int tid = threadIdx.x;
+    int n0[3] = {0, 0, 0}, W[3] = {1, 1, 1};
+    tile_geometry<2>(ch, a.tpd, a.tile, M2, n0, W);
+    const int T0 = a.tile[0], T1 = a.tile[1];
+    if constexpr (std::is_same<R, float>::value) {
+        for (int e = tid; e < m * kPolyCoef; e += blockDim.x) coef[e] = a.poly[e];
+    }
+    const int lane = tid & 63, wv = tid >> 6;
+    const int c1 = lane & 31;
+    const int cb = 8 * wv + 4 * (lane >> 5);
+    // tile rows whose nodes reach box rows [8 wv, 8 wv + 8)
+    const int rlo = max(0, 8 * wv - M2 + 1), rhi = min(T0 - 1, 8 * wv + 7);
+    Cx<R> acc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = Cx<R>{R(0), R(0)};
+
+    const R* __restrict__ xs = static_cast<const R*>(a.xs);
+    const Cx<R>* __restrict__ g = static_cast<const Cx<R>*>(a.g);
+    const R beta = R(a.beta), cbeta = R(a.cb), inv_m2 = R(1) / R(m * m);
+    for (int b0 = 0; b0 < ch.z; b0 += NB) {
+        const int nb = min(NB, ch.z - b0);
+        __syncthreads();   // coefficients staged / previous batch consumed
+        {
+            vec_t* z = reinterpret_cast<vec_t*>(w0s);
+            for (int e = tid; e < 64 * P / VEC; e += blockDim.x) z[e] = vec_t(R(0));
+        }
+        __syncthreads();
+        if (tid < nb) {
+            {
+                const int64_t j = int64_t(ch.y) + b0 + tid;
+                R theta[2];
+                int r[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    int nc;
+                    cell_of<R>(xs[j * 2 + t], L, nc, theta[t]);
+                    r[t] = nc + L / 2 - n0[t];
+                }
+                R w[2][M2];
+                if constexpr (std::is_same<R, float>::value) {
+                    weights_poly<2, M2, kPolyCoef>(theta, coef, w);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) weights<R, M2, METHOD>(theta[t], beta, cbeta, inv_m2, w[t]);
+                }
+#pragma unroll
+                for (int o = 0; o < M2; ++o) {
+                    w0s[(r[0] + o) * P + tid] = w[0][o];
+                    w1s[(r[1] + o) * P + tid] = w[1][o];
+                }
+                gv[tid] = g[a.perm[j]];
+                key[tid] = r[0] * T1 + r[1];
+            }
+        } else if (tid < NB) {
+            gv[tid] = Cx<R>{R(0), R(0)};   // past the batch: group ends read it
+        }
+        __syncthreads();
+        // rowstart[r] = first batch position in tile row r or later (the batch is sorted)
+        if (tid <= T0) {
+            const int c = tid * T1;
+            int lo = 0, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key[mid] < c) lo = mid + 1;
+                else hi = mid;
+            }
+            rowstart[tid] = lo;
+        }
+        __syncthreads();
+        const int js = rlo <= rhi ? rowstart[rlo] & ~(VEC - 1) : 0;
+        const int je = rlo <= rhi ? rowstart[rhi + 1] : 0;
+        const R* w1p = w1s + c1 * P;
+        const R* w0p = w0s + cb * P;
+#pragma unroll 2
+        for (int j = js; j < je; j += VEC) {
+            const vec_t wl = *reinterpret_cast<const vec_t*>(w1p + j);
+            vec_t w0[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) w0[k] = *reinterpret_cast<const vec_t*>(w0p + k * P + j);
+            Cx<R> gq[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) gq[q] = gv[j + q];
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                const R are = wl[q] * gq[q].re, aim = wl[q] * gq[q].im;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    acc[k].re = dev_fma(w0[k][q], are, acc[k].re);
+                    acc[k].im = dev_fma(w0[k][q], aim, acc[k].im);
+                }
+            }
+        }
+    }
+
+    if (c1 >= W[1]) return;
+    R* __restrict__ grid = static_cast<R*>(a.grid);
+    int p1 = n0[1] - m + 1 + c1;
+    if (METHOD == 1) p1 = (p1 % L + L) % L;
+    else if (p1 < 0 || p1 >= L) return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c0 = cb + k;
+        if (c0 >= W[0]) break;
+        if (acc[k].re == R(0) && acc[k].im == R(0)) continue;
+        int p0 = n0[0] - m + 1 + c0;
+        if (METHOD == 1) p0 = (p0 % L + L) % L;
+        else if (p0 < 0 || p0 >= L) continue;
+        const int64_t gidx = int64_t(p0) * L + p1;
+        hbm_add(grid + 2 * gidx, acc[k].re);
+        hbm_add(grid + 2 * gidx + 1, acc[k].im);
+    }
+}
+
 template <typename R, int D, int M2>
 __global__ void __launch_bounds__(256) k_grad_x(SpreadArgs a) {
     extern __shared__ unsigned char smem_raw[];
@@ -492,6 +640,20 @@ KFn spread_os_m(int m) {
 }
 
 template <typename R, int METHOD>
+KFn spread_rows_m(int m) {
+    switch (m) {
+        case 2: return k_spread_rows<R, 4, METHOD>;
+        case 3: return k_spread_rows<R, 6, METHOD>;
+        case 4: return k_spread_rows<R, 8, METHOD>;
+        case 5: return k_spread_rows<R, 10, METHOD>;
+        case 6: return k_spread_rows<R, 12, METHOD>;
+        case 7: return k_spread_rows<R, 14, METHOD>;
+        case 8: return k_spread_rows<R, 16, METHOD>;
+        default: return nullptr;
+    }
+}
+
+template <typename R, int METHOD>
 KFn spread_os_d(int d, int m) {
     if (d == 1) return spread_os_m<R, 1, METHOD>(m);
     if (d == 2) return spread_os_m<R, 2, METHOD>(m);
@@ -557,10 +719,15 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
     const size_t rs = p.prec == BL_F64 ? 8 : 4;
     const size_t os_lds = ((rs * p.d * 2 * p.m * kOsBatch + 2 * rs * kOsBatch + 4 * kOsBatch +
                             4 * size_t(ncell + 1) + 15) & ~size_t(15)) + sizeof(float) * kMaxM * kPolyCoef;
-    const bool use_os = box <= int64_t(kp) * kOsThreads && os_lds <= 64 * 1024 &&
+    const bool use_rows = p.d == 2 && p.tile[0] + 2 * p.m - 1 <= 32 && p.tile[1] + 2 * p.m - 1 <= 32 &&
+                          std::getenv("BL_SPREAD_ATOMIC") == nullptr && std::getenv("BL_SPREAD_OS") == nullptr;
+    const bool use_os = !use_rows && box <= int64_t(kp) * kOsThreads && os_lds <= 64 * 1024 &&
                         std::getenv("BL_SPREAD_ATOMIC") == nullptr;
     KFn fn;
-    if (use_os) {
+    if (use_rows) {
+        if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_rows_m<double, 1>(p.m) : spread_rows_m<double, 0>(p.m);
+        else fn = p.method == BL_NFFT ? spread_rows_m<float, 1>(p.m) : spread_rows_m<float, 0>(p.m);
+    } else if (use_os) {
         if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_os_d<double, 1>(p.d, p.m) : spread_os_d<double, 0>(p.d, p.m);
         else fn = p.method == BL_NFFT ? spread_os_d<float, 1>(p.d, p.m) : spread_os_d<float, 0>(p.d, p.m);
     } else {
@@ -571,7 +738,8 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
         set_error("no spreading kernel for this (d, m)");
         return BL_EUNSUPPORTED;
     }
-    const size_t lds = use_os ? os_lds : box_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
+    const size_t lds = use_rows ? (p.prec == BL_F64 ? rows_lds_bytes<double>() : rows_lds_bytes<float>())
+                       : use_os ? os_lds : box_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);

@@ -222,6 +222,28 @@ def test_adjoint_matches_oracle(d, M, L, m, N, prec, method):
     assert O.rel_err_inf(a, ao) <= (1e-12 if prec == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("d,M,L,m,N,tile", [(1, 64, 128, 5, 1500, None), (2, 32, 64, 6, 40000, None),
+                                            (2, 64, 128, 8, 5000, None), (2, 64, 128, 4, 5000, 24),
+                                            (3, 16, 32, 3, 1500, None)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kernel", ["default", "BL_SPREAD_OS", "BL_SPREAD_ATOMIC"])
+def test_adjoint_spread_kernels(d, M, L, m, N, tile, prec, kernel, monkeypatch):
+    """Each spreading kernel (d = 2 row kernel, output-stationary kernel, LDS-atomic kernel)
+    against the oracle, with several node batches per chunk (N = 40000 puts about 2500
+    nodes in each of 16 tiles) and boxes that do not fit the d = 2 row kernel (tile 24)."""
+    if kernel != "default":
+        monkeypatch.setenv(kernel, "1")
+    if tile is not None:
+        monkeypatch.setenv("BL_TILE", str(tile))
+    p = W.custom_problem(d, M, L, m, N, seed=500 + d + m, precision="f32" if prec != "f64" else "f64",
+                         with_targets=True)
+    plan = make_plan(p, prec, "nfft")
+    plan.set_nodes(dev_real(p.x, prec))
+    a = host(plan.adjoint(dev_cplx(p.y, prec)))
+    ao = O.adjoint_nfft(p.y, p.x, M, L, m)
+    assert O.rel_err_inf(a, ao) <= (1e-12 if prec == "f64" else 1e-5)
+
+
 @pytest.mark.parametrize("d,M,L,m,N", [(1, 64, 128, 5, 1500), (2, 32, 64, 4, 3000),
                                        (3, 16, 32, 3, 1500), (2, 256, 512, 6, 20000)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
