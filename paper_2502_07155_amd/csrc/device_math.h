@@ -243,6 +243,65 @@ __device__ __forceinline__ void weights_poly(const float* theta, const float* co
     }
 }
 
+// Weights and their theta-derivatives from the polynomials of weights_poly: the derivative
+// of the approximant itself (for the edge pair, of sqrt(1 - theta) K(theta) and
+// sqrt(theta) K(1 - theta), whose derivatives grow like 1 / sqrt at the support end).
+// At theta = 0 the edge derivative is zero: the window's support ends there.
+template <int D, int M2, int NC>
+__device__ __forceinline__ void weights_poly_deriv(const float* theta, const float* coef,
+                                                   float (*w)[M2], float (*dw)[M2]) {
+    constexpr int m = M2 / 2;
+    constexpr int NE = NC / 2;
+    static_assert(NC % 8 == 4 || NC % 8 == 0, "coefficients are read as float4");
+    float t[D], t2[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        t[d] = theta[d] - 0.5f;
+        t2[d] = t[d] * t[d];
+    }
+#pragma unroll
+    for (int o = 0; o < m; ++o) {
+        float c[NC];
+#pragma unroll
+        for (int q = 0; q < NC / 4; ++q) {
+            const float4 v = reinterpret_cast<const float4*>(coef + o * NC)[q];
+            c[4 * q] = v.x;
+            c[4 * q + 1] = v.y;
+            c[4 * q + 2] = v.z;
+            c[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            // E(t^2), O(t^2) and their derivatives in t^2 by Horner
+            float E = c[NE - 1], Od = c[NC - 1], dE = 0.0f, dO = 0.0f;
+#pragma unroll
+            for (int k = NE - 2; k >= 0; --k) {
+                dE = fmaf(dE, t2[d], E);
+                E = fmaf(E, t2[d], c[k]);
+                dO = fmaf(dO, t2[d], Od);
+                Od = fmaf(Od, t2[d], c[NE + k]);
+            }
+            // p(t) = E + t O, q(t) = p(-t); dp/dtheta = A + B, dq/dtheta = A - B
+            const float tO = t[d] * Od;
+            const float A = 2.0f * t[d] * dE, B = fmaf(2.0f * t2[d], dO, Od);
+            const float p = E + tO, q = E - tO, dp = A + B, dq = A - B;
+            if (o == 0) {
+                const float s1 = __builtin_amdgcn_sqrtf(1.0f - theta[d]);
+                const float s0 = __builtin_amdgcn_sqrtf(theta[d]);
+                w[d][0] = s1 * p;
+                dw[d][0] = fmaf(s1, dp, -0.5f * p * __builtin_amdgcn_rcpf(s1));
+                w[d][M2 - 1] = s0 * q;
+                dw[d][M2 - 1] = theta[d] > 0.0f ? fmaf(s0, dq, 0.5f * q * __builtin_amdgcn_rcpf(s0)) : 0.0f;
+            } else {
+                w[d][o] = p;
+                w[d][M2 - 1 - o] = q;
+                dw[d][o] = dp;
+                dw[d][M2 - 1 - o] = dq;
+            }
+        }
+    }
+}
+
 // Double weights from polynomials in the same even/odd layout as weights_poly (NC/2 even
 // then NC/2 odd coefficients per offset pair, read from LDS as uniform double2 loads).
 template <int D, int M2, int NC>

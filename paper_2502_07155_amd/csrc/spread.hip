@@ -518,6 +518,10 @@ __global__ void __launch_bounds__(256) k_grad_x(SpreadArgs a) {
         }
         lds[e] = ok ? th[gidx] : Cx<R>{R(0), R(0)};
     }
+    float* coef = reinterpret_cast<float*>(smem_raw + ((size_t(total) * sizeof(Cx<R>) + 15) & ~size_t(15)));
+    if constexpr (std::is_same<R, float>::value) {
+        for (int e = threadIdx.x; e < m * kPolyCoef; e += blockDim.x) coef[e] = a.poly[e];
+    }
     __syncthreads();
 
     const R* __restrict__ xs = static_cast<const R*>(a.xs);
@@ -527,14 +531,19 @@ __global__ void __launch_bounds__(256) k_grad_x(SpreadArgs a) {
     for (int jj = threadIdx.x; jj < ch.z; jj += blockDim.x) {
         const int64_t j = int64_t(ch.y) + jj;
         R w[D][M2], dw[D][M2];
+        R theta[D];
         int r[3] = {0, 0, 0};
 #pragma unroll
         for (int t = 0; t < D; ++t) {
             int n;
-            R theta;
-            cell_of<R>(xs[j * D + t], L, n, theta);
+            cell_of<R>(xs[j * D + t], L, n, theta[t]);
             r[t] = n + L / 2 - n0[t];
-            weights_and_derivs<R, M2>(theta, beta, cb, inv_m2, w[t], dw[t]);
+        }
+        if constexpr (std::is_same<R, float>::value) {
+            weights_poly_deriv<D, M2, kPolyCoef>(theta, coef, w, dw);
+        } else {
+#pragma unroll
+            for (int t = 0; t < D; ++t) weights_and_derivs<R, M2>(theta[t], beta, cb, inv_m2, w[t], dw[t]);
         }
         Cx<R> der[3];
         if constexpr (D == 1) {
@@ -562,6 +571,13 @@ __global__ void __launch_bounds__(256) k_grad_x(SpreadArgs a) {
         } else {
             Plain<R> d0, d1, d2;
             const int base = (r[0] * W[1] + r[1]) * W[2] + r[2];
+            // first-dimension weights shifted down each step (no dynamic register index)
+            R w0v[M2], dw0v[M2];
+#pragma unroll
+            for (int o = 0; o < M2; ++o) {
+                w0v[o] = w[0][o];
+                dw0v[o] = dw[0][o];
+            }
 #pragma unroll 1
             for (int o0 = 0; o0 < M2; ++o0) {
                 Plain<R> pa, p1, p2;
@@ -578,9 +594,14 @@ __global__ void __launch_bounds__(256) k_grad_x(SpreadArgs a) {
                     p1.add(dw[1][o1], ra.value());
                     p2.add(w[1][o1], rd.value());
                 }
-                d0.add(dw[0][o0], pa.value());
-                d1.add(w[0][o0], p1.value());
-                d2.add(w[0][o0], p2.value());
+                d0.add(dw0v[0], pa.value());
+                d1.add(w0v[0], p1.value());
+                d2.add(w0v[0], p2.value());
+#pragma unroll
+                for (int o = 0; o + 1 < M2; ++o) {
+                    w0v[o] = w0v[o + 1];
+                    dw0v[o] = dw0v[o + 1];
+                }
             }
             der[0] = d0.value();
             der[1] = d1.value();
@@ -758,7 +779,7 @@ bl_status launch_grad_x(Plan& p, const void* g, void* gx) {
     a.g = g;
     a.grid = p.d_grid;
     a.gx = gx;
-    const size_t lds = box_bytes(p);
+    const size_t lds = box_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);
