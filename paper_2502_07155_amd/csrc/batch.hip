@@ -1,5 +1,5 @@
 // Batched d = 1 transforms (Algorithm 4.2) of many independent instances with their own
-// (M_i, L_i, m_i, N_i), executed as one hipGraph of two kernels.
+// (M_i, L_i, m_i, N_i), executed as one hipGraph (DFT kernels, then the short sums).
 //
 // Step 2 for arbitrary even L (not only powers of two) uses the chirp-z (Bluestein) form
 // of the transform (4.7): with u = e^{i pi / L} and k l = (k^2 + l^2 - (l-k)^2)/2,
@@ -10,9 +10,11 @@
 //   theta_l = u^{l^2} z[l mod P].
 // a_k = fhat(k) / (L psihat(k)) (step 1) and the chirps u^{k^2}, u^{l^2} are formed in FP64 on
 // the host (k^2 mod 2L in integers); H is computed on the host in FP64 and stored as float.
-// Each length-P DFT pair is split into R = P / S pieces of S <= 4096 points (a radix-R
-// decimation in frequency through global scratch); one 256-thread workgroup per piece
-// runs its two DFTs in LDS, and the last piece of an instance to finish combines them.
+// An instance with P <= 8192 runs both DFTs in LDS in one 512-thread workgroup.  A larger
+// one is split into R = P / S pieces of S <= 8192 points: k_batch_dif forms the pieces of
+// a radix-R decimation in frequency in global scratch, one workgroup per piece runs its
+// two DFTs in LDS, and k_batch_combine undoes the decimation for the output.  Work items
+// are ordered largest first.
 //
 // Step 3 runs one workgroup per work chunk of the instances' node tiles, as in the
 // single-transform short sums, with each chunk's instance parameters (L, m, window
