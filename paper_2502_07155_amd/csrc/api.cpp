@@ -220,7 +220,6 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     if (std::isnan(beta) || std::isinf(beta)) return fail(BL_EINVAL, "beta not finite");
     if (m < kMinM || m > kMaxM)
         return fail(BL_EUNSUPPORTED, "compiled short-sum kernels cover 2 <= m <= 8");
-    if (win != BL_WIN_SINH) return fail(BL_EUNSUPPORTED, "GPU kernels implement the sinh-type window");
     FftFactors fac16, fac4;
     if (L > (1 << 30) || !factor_length(int(L), 16, &fac16) || !factor_length(int(L), 4, &fac4))
         return fail(BL_EUNSUPPORTED, "per-plan FFT needs L a power of two, L >= 16");
@@ -278,13 +277,21 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
         tw32[v].resize(tw[v].size());
         for (size_t i = 0; i < tw[v].size(); ++i) tw32[v][i] = float(tw[v][i]);
     }
+    p.edge_k = edge_exponent(win);
     if (prec != BL_F64) {
         std::vector<double> pc;
         p.poly_err = fit_weight_polys(win, method, m, p.beta, kPolyCoef, &pc);
         p.poly.assign(pc.begin(), pc.end());
     } else {
         p.poly64_err = fit_weight_polys(win, method, m, p.beta, kPolyCoef64, &p.poly64);
-        p.use_poly64 = p.poly64_err <= 1e-13 && std::getenv("BL_EXACT_WEIGHTS") == nullptr;
+        if (win == BL_WIN_SINH) {
+            p.use_poly64 = p.poly64_err <= 1e-13 && std::getenv("BL_EXACT_WEIGHTS") == nullptr;
+        } else {
+            // the exact device weight formula is the sinh-type window's
+            if (p.poly64_err > 1e-13)
+                return cleanup(fail(BL_EUNSUPPORTED, "FP64 weights of this window need a polynomial fit within 1e-13"));
+            p.use_poly64 = true;
+        }
     }
 
     size_t total = 0;
@@ -417,6 +424,8 @@ bl_status bl_grad_x(bl_plan plan, const void* g_dev, void* gx_dev) {
     BL_TRY(check_plan(plan));
     Plan& p = plan->p;
     if (p.method != BL_SHANNON) return fail(BL_EUNSUPPORTED, "grad_x is implemented for BL_SHANNON");
+    if (p.prec == BL_F64 && p.win != BL_WIN_SINH)
+        return fail(BL_EUNSUPPORTED, "FP64 grad_x is implemented for the sinh-type window");
     if (!p.have_theta) return fail(BL_ESTATE, "bl_grad_x needs the samples of a preceding bl_forward");
     if (p.N > 0 && (!g_dev || !gx_dev)) return fail(BL_EINVAL, "NULL buffer");
     return launch_grad_x(p, g_dev, gx_dev);

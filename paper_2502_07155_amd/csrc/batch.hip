@@ -574,7 +574,7 @@ __device__ __forceinline__ void batch_gather_chunk(const BGatherArgs& a, const i
                              // per node instead of holding all of them in registers
                              int opaque = 0;
                              asm volatile("" : "+s"(opaque));
-                             dev::weights_poly<1, M2, kPolyCoef>(theta, coef + opaque, w);
+                             dev::weights_poly<1, M2, kPolyCoef>(theta, coef + opaque, w, 1.0f);
                              typename std::conditional<ACC == 1, dev::WideAcc<float>, dev::Plain<float>>::type acc;
 #pragma unroll
                              for (int o = 0; o < M2; ++o) acc.add(w[0][o], lds[r + o]);

@@ -96,6 +96,7 @@ struct Plan {
     std::vector<double> poly64;
     double poly64_err = 0.0;
     bool use_poly64 = false;
+    double edge_k = 1.0;           // edge exponent of the weight polynomials (edge_exponent)
     // Inverse-direction twiddles for the adjoint are the conjugates; computed in kernel.
 
     // FFT ping-pong buffers and the grid of theta (L^d complex).
@@ -167,6 +168,7 @@ bool factor_length(int L, int E, FftFactors* out);
 void stage_twiddles(const FftFactors& fac, const std::vector<double>& tw, std::vector<double>* out,
                     int* off);
 double window_value(bl_window win, bl_method method, int m, double beta, double u);
+double edge_exponent(bl_window win);
 double fit_weight_polys(bl_window win, bl_method method, int m, double beta, int nc,
                         std::vector<double>* coef);
 

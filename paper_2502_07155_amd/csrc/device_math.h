@@ -195,13 +195,15 @@ __device__ __forceinline__ void weights_f32(float theta, const WinF32& wp, float
 // Float weights of D coordinates from polynomials (coefficients fitted on the host in
 // double).  psi is even, so offset 2m-1-o at theta equals offset o at 1 - theta, i.e. at
 // -t with t = theta - 1/2: one polynomial P_o(t) = E_o(t^2) + t O_o(t^2) gives both,
-// w[o] = E + t O and w[2m-1-o] = E - t O.  At the edge offsets the window has a square
-// root factor, psi(theta + m - 1) = sqrt(1 - theta) K(theta) with K analytic, so P_0
-// fits K and w[0] = sqrt(1 - theta) P_0(t), w[2m-1] = sqrt(theta) P_0(-t).  coef points
-// to LDS: per o, NC/2 even then NC/2 odd coefficients.
+// w[o] = E + t O and w[2m-1-o] = E - t O.  At the edge offsets the sinh-type window has a
+// square-root factor, psi(theta + m - 1) = sqrt(1 - theta) K(theta) with K analytic, so
+// P_0 fits K and w[0] = sqrt(1 - theta) P_0(t), w[2m-1] = sqrt(theta) P_0(-t).  The
+// factors are written sqrt(1 - ek theta) and sqrt(ek theta + 1 - ek): ek = 1 for that
+// window, ek = 0 (no factor) for the continuous Kaiser-Bessel window, which is smooth
+// there.  coef: per o, NC/2 even then NC/2 odd coefficients.
 template <int D, int M2, int NC>
 __device__ __forceinline__ void weights_poly(const float* theta, const float* coef,
-                                             float (*w)[M2]) {
+                                             float (*w)[M2], float ek) {
     constexpr int m = M2 / 2;
     constexpr int NE = NC / 2;
     static_assert(NC % 8 == 4 || NC % 8 == 0, "coefficients are read as float4");
@@ -233,8 +235,8 @@ __device__ __forceinline__ void weights_poly(const float* theta, const float* co
             const float tO = t[d] * Od;
             const float p = E + tO, q = E - tO;
             if (o == 0) {
-                w[d][0] = __builtin_amdgcn_sqrtf(1.0f - theta[d]) * p;
-                w[d][M2 - 1] = __builtin_amdgcn_sqrtf(theta[d]) * q;
+                w[d][0] = __builtin_amdgcn_sqrtf(fmaf(-ek, theta[d], 1.0f)) * p;
+                w[d][M2 - 1] = __builtin_amdgcn_sqrtf(fmaf(ek, theta[d], 1.0f - ek)) * q;
             } else {
                 w[d][o] = p;
                 w[d][M2 - 1 - o] = q;
@@ -244,12 +246,13 @@ __device__ __forceinline__ void weights_poly(const float* theta, const float* co
 }
 
 // Weights and their theta-derivatives from the polynomials of weights_poly: the derivative
-// of the approximant itself (for the edge pair, of sqrt(1 - theta) K(theta) and
-// sqrt(theta) K(1 - theta), whose derivatives grow like 1 / sqrt at the support end).
-// At theta = 0 the edge derivative is zero: the window's support ends there.
+// of the approximant itself (for the edge pair, of sqrt(1 - ek theta) K(theta) and
+// sqrt(ek theta + 1 - ek) K(1 - theta); with ek = 1 these grow like 1 / sqrt at the
+// support end).  Where the square root is zero the edge derivative is taken as zero: the
+// window's support ends there.
 template <int D, int M2, int NC>
 __device__ __forceinline__ void weights_poly_deriv(const float* theta, const float* coef,
-                                                   float (*w)[M2], float (*dw)[M2]) {
+                                                   float (*w)[M2], float (*dw)[M2], float ek) {
     constexpr int m = M2 / 2;
     constexpr int NE = NC / 2;
     static_assert(NC % 8 == 4 || NC % 8 == 0, "coefficients are read as float4");
@@ -286,12 +289,12 @@ __device__ __forceinline__ void weights_poly_deriv(const float* theta, const flo
             const float A = 2.0f * t[d] * dE, B = fmaf(2.0f * t2[d], dO, Od);
             const float p = E + tO, q = E - tO, dp = A + B, dq = A - B;
             if (o == 0) {
-                const float s1 = __builtin_amdgcn_sqrtf(1.0f - theta[d]);
-                const float s0 = __builtin_amdgcn_sqrtf(theta[d]);
+                const float s1 = __builtin_amdgcn_sqrtf(fmaf(-ek, theta[d], 1.0f));
+                const float s0 = __builtin_amdgcn_sqrtf(fmaf(ek, theta[d], 1.0f - ek));
                 w[d][0] = s1 * p;
-                dw[d][0] = fmaf(s1, dp, -0.5f * p * __builtin_amdgcn_rcpf(s1));
+                dw[d][0] = fmaf(s1, dp, -0.5f * ek * p * __builtin_amdgcn_rcpf(s1));
                 w[d][M2 - 1] = s0 * q;
-                dw[d][M2 - 1] = theta[d] > 0.0f ? fmaf(s0, dq, 0.5f * q * __builtin_amdgcn_rcpf(s0)) : 0.0f;
+                dw[d][M2 - 1] = s0 > 0.0f ? fmaf(s0, dq, 0.5f * ek * q * __builtin_amdgcn_rcpf(s0)) : 0.0f;
             } else {
                 w[d][o] = p;
                 w[d][M2 - 1 - o] = q;
@@ -306,7 +309,7 @@ __device__ __forceinline__ void weights_poly_deriv(const float* theta, const flo
 // then NC/2 odd coefficients per offset pair, read from LDS as uniform double2 loads).
 template <int D, int M2, int NC>
 __device__ __forceinline__ void weights_poly64(const double* theta, const double* coef,
-                                               double (*w)[M2]) {
+                                               double (*w)[M2], double ek) {
     constexpr int m = M2 / 2;
     constexpr int NE = NC / 2;
     static_assert(NC % 2 == 0 && NE % 2 == 0, "coefficients are read as double2");
@@ -330,8 +333,8 @@ __device__ __forceinline__ void weights_poly64(const double* theta, const double
             const double tO = t * Od;
             const double p = E + tO, q = E - tO;
             if (o == 0) {
-                w[d][0] = sqrt(1.0 - theta[d]) * p;
-                w[d][M2 - 1] = sqrt(theta[d]) * q;
+                w[d][0] = sqrt(fma(-ek, theta[d], 1.0)) * p;
+                w[d][M2 - 1] = sqrt(fma(ek, theta[d], 1.0 - ek)) * q;
             } else {
                 w[d][o] = p;
                 w[d][M2 - 1 - o] = q;

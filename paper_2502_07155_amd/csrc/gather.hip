@@ -224,6 +224,7 @@ struct GatherArgs {
     alignas(16) float poly[kMaxM * kPolyCoef];   // float weight polynomials (see weights_poly)
     alignas(16) double poly64[kMaxM * kPolyCoef64];   // double ones (see weights_poly64)
     int use_poly64;
+    float edge_k;   // edge exponent of the weight polynomials
 };
 
 template <typename R, int D, int M2, int ACC, int METHOD>
@@ -338,14 +339,14 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
         if constexpr (std::is_same<R, float>::value) {
             // m <= 6: coefficients straight from the kernel arguments (SGPRs); larger m
             // would spill SGPRs, so those read them from LDS (broadcast).
-            if constexpr (M2 <= 12) weights_poly<D, M2, kPolyCoef>(theta, a.poly, w);
-            else weights_poly<D, M2, kPolyCoef>(theta, coef, w);
+            if constexpr (M2 <= 12) weights_poly<D, M2, kPolyCoef>(theta, a.poly, w, a.edge_k);
+            else weights_poly<D, M2, kPolyCoef>(theta, coef, w, a.edge_k);
         } else if (a.use_poly64) {
             // An opaque zero offset keeps the (uniform, LDS) coefficient loads inside the
             // node loop instead of holding every coefficient in registers.
             int opaque = 0;
             asm volatile("" : "+s"(opaque));
-            weights_poly64<D, M2, kPolyCoef64>(theta, coef64 + opaque, w);
+            weights_poly64<D, M2, kPolyCoef64>(theta, coef64 + opaque, w, double(a.edge_k));
         } else {
 #pragma unroll
             for (int t = 0; t < D; ++t)
@@ -632,6 +633,7 @@ bl_status launch_gather(Plan& p, const void* theta, void* f) {
     for (size_t i = 0; i < p.poly.size() && i < size_t(kMaxM * kPolyCoef); ++i) a.poly[i] = p.poly[i];
     for (size_t i = 0; i < p.poly64.size() && i < size_t(kMaxM * kPolyCoef64); ++i) a.poly64[i] = p.poly64[i];
     a.use_poly64 = p.use_poly64 ? 1 : 0;
+    a.edge_k = float(p.edge_k);
     const size_t lds = gather_lds_bytes(p) + 16 + sizeof(double) * kMaxM * kPolyCoef64;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));

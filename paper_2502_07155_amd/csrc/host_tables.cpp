@@ -160,10 +160,16 @@ double window_value(bl_window win, bl_method method, int m, double beta, double 
     return v;
 }
 
+// Edge exponent k of the weight polynomials: the edge pair is sqrt(1 - k theta) K(theta)
+// and sqrt(k theta + 1 - k) K(1 - theta).  The sinh-type window behaves like a square
+// root at the end of its support (k = 1); the continuous Kaiser-Bessel window like
+// 1 - q^2, which is smooth (k = 0: no factor).
+double edge_exponent(bl_window win) { return win == BL_WIN_SINH ? 1.0 : 0.0; }
+
 // Polynomials for the float short-sum weights.  Offset o carries u = theta + m - 1 - o,
 // theta in [0, 1].  For o = 1..m-1 the weight itself, for o = 0 the factor
-// K(theta) = w_0(theta) / sqrt(1 - theta) (analytic: the window's square-root behaviour
-// at |u| = m is taken out).  Each is interpolated at nc Chebyshev points of theta in
+// K(theta) = w_0(theta) / sqrt(1 - k theta) (for the sinh window the square-root
+// behaviour at |u| = m is taken out).  Each is interpolated at nc Chebyshev points of theta in
 // [0, 1], converted to monomials in t = theta - 1/2 and stored as nc/2 even then nc/2
 // odd coefficients (the kernel uses w_{2m-1-o}(theta) = w_o(1 - theta)).  Returns the
 // largest deviation of the resulting weights from the exact ones, all 2m offsets, in
@@ -181,9 +187,10 @@ double fit_weight_polys(bl_window win, bl_method method, int m, double beta, int
             if (j > 0) v += 2.0 * T[k][j - 1];
             T[k + 1][j] = v;
         }
+    const double k = edge_exponent(win);
     auto target = [&](int o, double th) {
         const double w = window_value(win, method, m, beta, th + (m - 1 - o));
-        return o == 0 ? w / std::sqrt(1.0 - th) : w;
+        return o == 0 ? w / std::sqrt(1.0 - k * th) : w;
     };
     double worst = 0.0;
     std::vector<double> mono(n);
@@ -211,7 +218,7 @@ double fit_weight_polys(bl_window win, bl_method method, int m, double beta, int
                 double acc = 0.0;
                 for (int j = n - 1; j >= 0; --j) acc = acc * t + mono[j];
                 double wv;
-                if (o == 0) wv = acc * std::sqrt(side == 0 ? 1.0 - th : th);
+                if (o == 0) wv = acc * std::sqrt(side == 0 ? 1.0 - k * th : k * th + 1.0 - k);
                 else wv = acc;
                 const int oo = side == 0 ? o : 2 * m - 1 - o;
                 worst = std::max(worst, std::fabs(wv - window_value(win, method, m, beta, th + (m - 1 - oo))));

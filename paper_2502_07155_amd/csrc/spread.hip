@@ -42,6 +42,9 @@ struct SpreadArgs {
     double beta, cb;
     WinF32 wf;
     float poly[kMaxM * kPolyCoef];
+    alignas(16) double poly64[kMaxM * kPolyCoef64];   // double weight polynomials
+    int use_poly64;          // double kernels: weights from poly64 instead of the exact form
+    float edge_k;            // edge exponent of the weight polynomials
 };
 
 template <typename R>
@@ -100,7 +103,9 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
             r[t] = n + L / 2 - n0[t];
         }
         if constexpr (std::is_same<R, float>::value) {
-            weights_poly<D, M2, kPolyCoef>(theta, coef, w);
+            weights_poly<D, M2, kPolyCoef>(theta, coef, w, a.edge_k);
+        } else if (a.use_poly64) {
+            weights_poly64<D, M2, kPolyCoef64>(theta, a.poly64, w, double(a.edge_k));
         } else {
 #pragma unroll
             for (int t = 0; t < D; ++t) weights<R, M2, METHOD>(theta[t], beta, cb, inv_m2, w[t]);
@@ -227,7 +232,9 @@ __global__ void __launch_bounds__(kOsThreads) k_spread_os(SpreadArgs a) {
             }
             R w[D][M2];
             if constexpr (std::is_same<R, float>::value) {
-                weights_poly<D, M2, kPolyCoef>(theta, coef, w);
+                weights_poly<D, M2, kPolyCoef>(theta, coef, w, a.edge_k);
+            } else if (a.use_poly64) {
+                weights_poly64<D, M2, kPolyCoef64>(theta, a.poly64, w, double(a.edge_k));
             } else {
 #pragma unroll
                 for (int t = 0; t < D; ++t) weights<R, M2, METHOD>(theta[t], beta, cb, inv_m2, w[t]);
@@ -418,7 +425,9 @@ __global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
                 }
                 R w[2][M2];
                 if constexpr (std::is_same<R, float>::value) {
-                    weights_poly<2, M2, kPolyCoef>(theta, coef, w);
+                    weights_poly<2, M2, kPolyCoef>(theta, coef, w, a.edge_k);
+                } else if (a.use_poly64) {
+                    weights_poly64<2, M2, kPolyCoef64>(theta, a.poly64, w, double(a.edge_k));
                 } else {
 #pragma unroll
                     for (int t = 0; t < 2; ++t) weights<R, M2, METHOD>(theta[t], beta, cbeta, inv_m2, w[t]);
@@ -540,7 +549,7 @@ __global__ void __launch_bounds__(256) k_grad_x(SpreadArgs a) {
             r[t] = n + L / 2 - n0[t];
         }
         if constexpr (std::is_same<R, float>::value) {
-            weights_poly_deriv<D, M2, kPolyCoef>(theta, coef, w, dw);
+            weights_poly_deriv<D, M2, kPolyCoef>(theta, coef, w, dw, a.edge_k);
         } else {
 #pragma unroll
             for (int t = 0; t < D; ++t) weights_and_derivs<R, M2>(theta[t], beta, cb, inv_m2, w[t], dw[t]);
@@ -712,6 +721,9 @@ SpreadArgs make_args(const Plan& p) {
     a.cb = 1.0 / (-std::expm1(-2.0 * p.beta));
     a.wf = make_win_f32(p);
     for (size_t i = 0; i < p.poly.size() && i < size_t(kMaxM * kPolyCoef); ++i) a.poly[i] = p.poly[i];
+    for (size_t i = 0; i < p.poly64.size() && i < size_t(kMaxM * kPolyCoef64); ++i) a.poly64[i] = p.poly64[i];
+    a.use_poly64 = p.use_poly64 ? 1 : 0;
+    a.edge_k = float(p.edge_k);
     return a;
 }
 

@@ -308,3 +308,72 @@ def test_graph_replays_match_eager_launches():
         if rep == 3:
             graph.set_nodes(x)
     assert O.rel_err_inf(host(ref), O.forward_shannon(p.fhat, p.x, p.L, p.m)) <= 1e-6
+
+
+# Continuous Kaiser-Bessel window (Remark 3.1): the same kernels with the window's own
+# polynomial fits (no square-root edge factor: the window behaves like 1 - q^2 at the end
+# of its support), against the oracle's cKB window and transforms.
+CKB = [(1, 64, 128, 5, 1500), (2, 32, 64, 4, 3000), (2, 64, 128, 6, 4000), (3, 16, 32, 3, 1500)]
+
+
+def ckb_plan(p, prec, method="shannon"):
+    from paper_2502_07155_amd import Plan
+    return Plan(p.d, p.M, p.L, p.m, window="ckb", precision=prec, method=method)
+
+
+@pytest.mark.parametrize("d,M,L,m,N", CKB)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32c"])
+@pytest.mark.parametrize("method", ["shannon", "nfft"])
+def test_ckb_forward_matches_oracle(d, M, L, m, N, prec, method):
+    p = W.custom_problem(d, M, L, m, N, seed=600 + d + m, precision="f32" if prec != "f64" else "f64")
+    plan = ckb_plan(p, prec, method)
+    plan.set_nodes(dev_real(p.x, prec))
+    f = host(plan.forward(dev_cplx(p.fhat, prec)))
+    theta = host(plan.theta())
+    if method == "shannon":
+        fo, _, tho = O.forward_shannon(p.fhat, p.x, L, m, win="ckb", return_stages=True)
+    else:
+        fo, _, tho = O.forward_nfft(p.fhat, p.x, L, m, win="ckb", return_stages=True)
+    print(f"ckb d={d} M={M} L={L} m={m} {prec} {method}: theta {O.rel_err_inf(theta, tho):.2e} "
+          f"f {O.rel_err_inf(f, fo):.2e}")
+    assert O.rel_err_inf(theta, tho) <= THETA_TOL[prec]
+    assert O.rel_err_inf(f, fo) <= TOL[prec]
+
+
+@pytest.mark.parametrize("d,M,L,m,N", CKB)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("method", ["shannon", "nfft"])
+def test_ckb_adjoint_matches_oracle(d, M, L, m, N, prec, method):
+    p = W.custom_problem(d, M, L, m, N, seed=700 + d + m, precision="f32" if prec != "f64" else "f64",
+                         with_targets=True)
+    plan = ckb_plan(p, prec, method)
+    plan.set_nodes(dev_real(p.x, prec))
+    a = host(plan.adjoint(dev_cplx(p.y, prec)))
+    if method == "shannon":
+        ao = O.adjoint_shannon(p.y, p.x, M, L, m, win="ckb")
+    else:
+        ao = O.adjoint_nfft(p.y, p.x, M, L, m, win="ckb")
+    assert O.rel_err_inf(a, ao) <= (1e-12 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("d,M,L,m,N", CKB)
+def test_ckb_grad_x_matches_oracle(d, M, L, m, N):
+    p = W.custom_problem(d, M, L, m, N, seed=800 + d + m, precision="f32", with_targets=True)
+    plan = ckb_plan(p, "f32")
+    plan.set_nodes(dev_real(p.x, "f32"))
+    f = plan.forward(dev_cplx(p.fhat, "f32"))
+    G = 2 * (f - dev_cplx(p.y, "f32"))
+    gx = host(plan.grad_x(G))
+    go = O.grad_x_shannon(p.fhat, host(G), p.x, L, m, win="ckb")
+    assert O.rel_err_inf(gx, go) <= 2e-5
+
+
+def test_ckb_fp64_grad_x_is_refused():
+    from paper_2502_07155_amd._lib import BLNFFTError
+    p = W.custom_problem(2, 32, 64, 4, 500, seed=9, precision="f64", with_targets=True)
+    plan = ckb_plan(p, "f64")
+    plan.set_nodes(dev_real(p.x, "f64"))
+    f = plan.forward(dev_cplx(p.fhat, "f64"))
+    with pytest.raises(BLNFFTError) as e:
+        plan.grad_x(f)
+    assert e.value.status == 6
