@@ -1,7 +1,8 @@
 """FP64 CPU oracle (test infrastructure only).
 
-Only the test suite, the smoke check and the benchmark's CPU-baseline leg may import
-this package.  It shares no code with the GPU library.
+Only the test suite, the smoke check and the benchmark's oracle leg (its CPU baseline
+and its error checks against this oracle) may import this package.  It shares no code
+with the GPU library.
 """
 from .blnfft_oracle import *  # noqa: F401,F403
 from .blnfft_oracle import (  # noqa: F401
@@ -9,6 +10,6 @@ from .blnfft_oracle import (  # noqa: F401
     dense_B, dense_F, dense_D, deconvolve_pad, direct_sum, dirichlet, example51_f,
     forward_nfft, forward_shannon, gather_nfft, gather_shannon, grad_x_shannon,
     grad_x_from_theta,
-    in_truncated_domain, inverse_fft_step, phi_g, phihat1, psi_g, psihat1,
+    in_truncated_domain, inverse_fft_step, node_offsets, phi_g, phihat1, psi_g, psihat1,
     rel_err_inf, rel_err_l2, scaled_offset, sinc_pi, spread_shannon,
 )

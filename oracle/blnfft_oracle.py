@@ -1,8 +1,8 @@
 """FP64 CPU oracle for the NFFT-like procedure for bandlimited functions
 (Kircheis & Potts, "Nonequispaced fast Fourier transforms for bandlimited functions").
 
-TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the benchmark's CPU
-baseline may import or run this module.  The GPU library never calls it, shares no code
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the benchmark's oracle
+leg (its CPU baseline and its error checks) may import or run this module.  The GPU library never calls it, shares no code
 with it, and must fail loudly rather than fall back to it.
 
 Everything here is plain, slow and written to be checked against the paper by eye:
@@ -121,20 +121,31 @@ def default_beta(M: int, L: int, m: int, method: str = "shannon") -> float:
     raise ValueError(method)
 
 
-def _root(q: np.ndarray) -> np.ndarray:
-    """sqrt(1 - q^2) for |q| <= 1, evaluated as sqrt((1-q)(1+q))."""
-    return np.sqrt(np.maximum((1.0 - q) * (1.0 + q), 0.0))
+def _edge(t, m: int, e):
+    """Distance m - |t| to the end of the support: the given e, else formed from t."""
+    t = np.asarray(t, dtype=np.float64)
+    return (m - np.abs(t)) if e is None else np.asarray(e, dtype=np.float64)
 
 
-def phi_g(t, m: int, beta: float, win: str = "sinh") -> np.ndarray:
+def _root(t, m: int, e) -> np.ndarray:
+    """sqrt(1 - (t/m)^2) for |t| <= m, as sqrt(e (m + |t|)) / m with e = m - |t|: near the
+    end of the support the value depends on e only, which callers can pass exactly."""
+    t = np.asarray(t, dtype=np.float64)
+    return np.sqrt(np.maximum(e, 0.0) * (m + np.abs(t))) / m
+
+
+def phi_g(t, m: int, beta: float, win: str = "sinh", e=None) -> np.ndarray:
     """Window phi in grid units, zero outside |t| <= m.
 
     sinh: sinh(beta*sqrt(1-(t/m)^2)) / sinh(beta)               eq. (3.4)
-    ckb:  (I0(beta*sqrt(1-(t/m)^2)) - 1) / (I0(beta) - 1)       Remark 3.1"""
+    ckb:  (I0(beta*sqrt(1-(t/m)^2)) - 1) / (I0(beta) - 1)       Remark 3.1
+    e: optional m - |t| computed without the rounding of t (see node_offsets); the sinh
+    window grows like sqrt(m - |t|) at the end of its support, so there that distance
+    decides the value."""
     t = np.asarray(t, dtype=np.float64)
-    q = t / m
-    inside = np.abs(q) <= 1.0
-    s = _root(np.where(inside, q, 0.0))
+    e = _edge(t, m, e)
+    inside = e >= 0.0
+    s = _root(t, m, e)
     if win == "sinh":
         val = np.sinh(beta * s) / np.sinh(beta)
     elif win == "ckb":
@@ -144,15 +155,15 @@ def phi_g(t, m: int, beta: float, win: str = "sinh") -> np.ndarray:
     return np.where(inside, val, 0.0)
 
 
-def dphi_g(t, m: int, beta: float, win: str = "sinh") -> np.ndarray:
+def dphi_g(t, m: int, beta: float, win: str = "sinh", e=None) -> np.ndarray:
     """d/dt of phi_g.  For sinh it behaves like 1/sqrt(m-|t|) at the edge; the value at
     |t| = m itself (and outside) is returned as 0 (it is only ever multiplied by a sinc
-    factor that vanishes there)."""
+    factor that vanishes there).  e as in phi_g."""
     t = np.asarray(t, dtype=np.float64)
-    q = t / m
-    inside = np.abs(q) < 1.0
-    qq = np.where(inside, q, 0.0)
-    s = _root(qq)
+    e = _edge(t, m, e)
+    inside = e > 0.0
+    qq = np.where(inside, t / m, 0.0)
+    s = _root(t, m, np.where(inside, e, 0.0))
     s_safe = np.where(inside, s, 1.0)
     dsdt = -(qq / m) / s_safe
     if win == "sinh":
@@ -165,16 +176,16 @@ def dphi_g(t, m: int, beta: float, win: str = "sinh") -> np.ndarray:
     return np.where(inside, val, 0.0)
 
 
-def psi_g(t, m: int, beta: float, win: str = "sinh") -> np.ndarray:
+def psi_g(t, m: int, beta: float, win: str = "sinh", e=None) -> np.ndarray:
     """Regularized sinc (4.2) in grid units: psi(u) = sinc(L pi u) phi(u), t = L u."""
-    return sinc_pi(t) * phi_g(t, m, beta, win)
+    return sinc_pi(t) * phi_g(t, m, beta, win, e)
 
 
-def dpsi_g(t, m: int, beta: float, win: str = "sinh") -> np.ndarray:
+def dpsi_g(t, m: int, beta: float, win: str = "sinh", e=None) -> np.ndarray:
     """d/dt of psi_g; zero at |t| >= m (psi is C^1 there)."""
     t = np.asarray(t, dtype=np.float64)
-    inside = np.abs(t) < m
-    val = dsinc_pi(t) * phi_g(t, m, beta, win) + sinc_pi(t) * dphi_g(t, m, beta, win)
+    inside = _edge(t, m, e) > 0.0
+    val = dsinc_pi(t) * phi_g(t, m, beta, win, e) + sinc_pi(t) * dphi_g(t, m, beta, win, e)
     return np.where(inside, val, 0.0)
 
 
@@ -267,18 +278,24 @@ def inverse_fft_step(thetahat: np.ndarray) -> np.ndarray:
     return np.fft.fftshift(np.fft.ifftn(np.fft.ifftshift(thetahat)))
 
 
-def _node_offsets(x_col: np.ndarray, L: int, m: int):
+def node_offsets(x_col: np.ndarray, L: int, m: int):
     """For one coordinate of every node: the 2m+1 candidate indices l = c + o,
-    o = -m..m, c = round(L x), and their grid offsets t = L x - l.
+    o = -m..m, c = round(L x), their grid offsets t = L x - l, and the distances
+    e = m - |L x - l| to the end of the window's support.
 
     Every l with |L x - l| <= m (the set J_{L,m}(x) of (4.8), per dimension) is among
-    the candidates because |L x - c| <= 1/2; candidates with |t| > m get window 0."""
+    the candidates because |L x - c| <= 1/2; candidates with |t| > m get window 0.
+    With t0 = L x - c (one rounding) and |t0| <= 1/2, |t| = |o| - sign(o) t0 for o != 0,
+    so e = (m - |o|) + sign(o) t0 is rounded once and exact where m - |o| = 0; the
+    rounded t itself would lose the distance of a node just inside the support end."""
     c = np.rint(L * x_col)
     t0 = scaled_offset(L, x_col, c)                     # L x - c, one rounding
     o = np.arange(-m, m + 1, dtype=np.float64)
     ell = c[:, None] + o[None, :]
     t = t0[:, None] - o[None, :]
-    return ell.astype(np.int64), t
+    e = np.where(o[None, :] == 0, m - np.abs(t0)[:, None],
+                 (m - np.abs(o))[None, :] + np.sign(o)[None, :] * t0[:, None])
+    return ell.astype(np.int64), t, e
 
 
 def gather_shannon(theta: np.ndarray, x: np.ndarray, L: int, m: int, beta: float,
@@ -294,9 +311,9 @@ def gather_shannon(theta: np.ndarray, x: np.ndarray, L: int, m: int, beta: float
         xs = x[s:s + chunk]
         idx, w = [], []
         for t in range(d):
-            ell, off = _node_offsets(xs[:, t], L, m)
+            ell, off, edge = node_offsets(xs[:, t], L, m)
             idx.append(ell + L // 2 + pad)
-            w.append(psi_g(off, m, beta, win))
+            w.append(psi_g(off, m, beta, win, edge))
         acc = np.zeros(xs.shape[0], dtype=np.complex128)
         for combo in itertools.product(range(2 * m + 1), repeat=d):
             wt = w[0][:, combo[0]].copy()
@@ -338,9 +355,9 @@ def gather_nfft(g: np.ndarray, x: np.ndarray, L: int, m: int, beta: float,
         xs = x[s:s + chunk]
         idx, w = [], []
         for t in range(d):
-            ell, off = _node_offsets(xs[:, t], L, m)
+            ell, off, edge = node_offsets(xs[:, t], L, m)
             idx.append(np.mod(ell + L // 2, L))
-            w.append(phi_g(off, m, beta, win))
+            w.append(phi_g(off, m, beta, win, edge))
         acc = np.zeros(xs.shape[0], dtype=np.complex128)
         for combo in itertools.product(range(2 * m + 1), repeat=d):
             wt = w[0][:, combo[0]].copy()
@@ -384,9 +401,9 @@ def spread_shannon(g: np.ndarray, x: np.ndarray, L: int, m: int, beta: float,
         gs = g[s:s + chunk]
         idx, w = [], []
         for t in range(d):
-            ell, off = _node_offsets(xs[:, t], L, m)
+            ell, off, edge = node_offsets(xs[:, t], L, m)
             idx.append(ell + L // 2 + pad)
-            w.append(psi_g(off, m, beta, win))
+            w.append(psi_g(off, m, beta, win, edge))
         for combo in itertools.product(range(2 * m + 1), repeat=d):
             wt = w[0][:, combo[0]].copy()
             flat = idx[0][:, combo[0]].copy()
@@ -447,10 +464,10 @@ def grad_x_from_theta(theta, G, x, L, m, beta, win, chunk=65536):
         xs = x[s:s + chunk]
         idx, w, dw = [], [], []
         for t in range(d):
-            ell, off = _node_offsets(xs[:, t], L, m)
+            ell, off, edge = node_offsets(xs[:, t], L, m)
             idx.append(ell + L // 2 + pad)
-            w.append(psi_g(off, m, beta, win))
-            dw.append(L * dpsi_g(off, m, beta, win))
+            w.append(psi_g(off, m, beta, win, edge))
+            dw.append(L * dpsi_g(off, m, beta, win, edge))
         der = np.zeros((xs.shape[0], d), dtype=np.complex128)
         for combo in itertools.product(range(2 * m + 1), repeat=d):
             vals = tp[tuple(idx[t][:, combo[t]] for t in range(d))]
@@ -475,9 +492,9 @@ def adjoint_nfft(g: np.ndarray, x: np.ndarray, M: int, L: int, m: int,
     acc = np.zeros(L ** d, dtype=np.complex128)
     idx, w = [], []
     for t in range(d):
-        ell, off = _node_offsets(x[:, t], L, m)
+        ell, off, edge = node_offsets(x[:, t], L, m)
         idx.append(np.mod(ell + L // 2, L))
-        w.append(phi_g(off, m, beta, win))
+        w.append(phi_g(off, m, beta, win, edge))
     for combo in itertools.product(range(2 * m + 1), repeat=d):
         wt = w[0][:, combo[0]].copy()
         flat = idx[0][:, combo[0]].copy()

@@ -35,6 +35,33 @@ def test_scaled_offset_matches_exact_rationals():
             assert abs(Fraction(float(gi)) - exact) <= abs(exact) * Fraction(1, 2 ** 52) + Fraction(1, 2 ** 80)
 
 
+def test_node_offsets_edge_distance_matches_exact_rationals():
+    """e = m - |L x - l| for every candidate l, including nodes a few ulps from a grid
+    point, where the window's square-root end makes that distance decide the weight."""
+    rng = np.random.default_rng(12)
+    for L, m in ((32, 5), (1024, 6), (4096, 8)):
+        k = rng.integers(-L // 2, L // 2, 40)
+        delta = np.concatenate([rng.random(20) - 0.5, 10.0 ** rng.uniform(-16, -12, 20)])
+        x = (k + delta) / L
+        ell, t, e = O.node_offsets(x, L, m)
+        for i in range(x.size):
+            for j in range(ell.shape[1]):
+                exact = Fraction(m) - abs(Fraction(L) * Fraction(float(x[i])) - Fraction(int(ell[i, j])))
+                assert abs(Fraction(float(e[i, j])) - exact) <= abs(exact) * Fraction(1, 2 ** 52) + Fraction(1, 2 ** 90)
+
+
+def test_window_near_the_end_of_its_support():
+    """Just inside |t| = m the sinh window is sinh(beta sqrt(1-(t/m)^2))/sinh(beta) with
+    1 - (t/m)^2 = e (2m - e) / m^2, e = m - |t|; passing e exactly keeps that value where
+    the rounded t cannot (eq. (3.4))."""
+    m, beta = 5, 7.853981633974483
+    for e in (6.7e-16, 1e-15, 3e-14, 1e-9):
+        t = -(m - e)                                   # rounds in double
+        exact = math.sinh(beta * math.sqrt(e * (2 * m - e)) / m) / math.sinh(beta)
+        got = float(O.phi_g(np.array([t]), m, beta, "sinh", np.array([e]))[0])
+        assert abs(got - exact) <= 1e-15 * exact
+
+
 def test_sinpi_special_values_and_small_arguments():
     n = np.arange(-20, 21, dtype=np.float64)
     assert np.all(O.sinpi(n) == 0.0)
