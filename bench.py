@@ -8,7 +8,11 @@ Headline workload: d=2, M=512, L=1024, m=5, N=1e6 uniform nodes, fhat complex no
 scaled by 1/(1+|k|^2), FP32 with compensated short sums ("f32c").  Beside it, unless
 --headline-only: the same workload in FP64 and with the classical NFFT (Algorithm 2.1),
 and the other workloads (d=1 FP64, d=3 clustered nodes, 512 batched d=1 instances, d=2
-forward + backward).  Prints one JSON line.
+forward + backward, the Example 5.1 sweep).  Prints one JSON line.
+
+The GPU legs keep seeded samples of their outputs; the oracle leg at the end (the only
+part of this file that calls the oracle) times the oracle for cpu_baseline and fills in
+each leg's error against it.  --headline-only and --no-cpu skip it.
 """
 from __future__ import annotations
 
@@ -43,12 +47,14 @@ def parse():
     ap.add_argument("--precision", default="f32c", choices=["f32c", "f32", "f64"])
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline workload only (no other legs, no CPU baseline)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle leg (CPU baseline and the error checks against the oracle)")
     ap.add_argument("--cpu-nodes", type=int, default=1_000_000,
                     help="nodes of the oracle's step-3 sample for the CPU baseline")
-    ap.add_argument("--leg", choices=["batched", "fwd_bwd", "nfft"],
-                    help="run only this leg (batched d=1 instances, d=2 forward + backward, or "
-                         "Algorithm 2.1 on the headline workload) and print its JSON")
+    ap.add_argument("--leg", choices=["batched", "fwd_bwd", "nfft", "example51"],
+                    help="run only this leg (batched d=1 instances, d=2 forward + backward, "
+                         "Algorithm 2.1 on the headline workload, or the Example 5.1 sweep) "
+                         "and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (for counter scaling)")
     ap.add_argument("--summarize-trace", metavar="DIR",
@@ -146,59 +152,147 @@ def run_plan(name: str, prec: str, steps: int, warmup: int, method: str = "shann
     return p, plan, f, ms, gms, plan_ms
 
 
-def accuracy(p, f, sample: int = 20000, method: str = "shannon", beta=None):
-    """Normwise relative errors against the oracle's fast form on a node sample."""
+def accuracy_check(rec: dict, p, f, sample: int = 20000, method: str = "shannon",
+                   beta: float = 0.0, key: str = "rel_err", l2: bool = False):
+    """Keep f on a seeded node sample; the returned check (run by the oracle leg) writes
+    the normwise relative error against the oracle's fast form into rec[key + '_inf']."""
     import numpy as np
 
-    import oracle as O
     import workloads as W
     idx = np.sort(W.rng_for(17).choice(p.N, size=min(sample, p.N), replace=False))
-    if method == "shannon":
-        ref = O.forward_shannon(p.fhat, p.x[idx], p.L, p.m, beta)
-    else:
-        ref = O.forward_nfft(p.fhat, p.x[idx], p.L, p.m, beta)
-    return O.rel_err_inf(f[idx], ref), O.rel_err_l2(f[idx], ref), idx
+    got, x, fhat, L, m = f[idx].copy(), p.x[idx].copy(), p.fhat, p.L, p.m
+
+    def check(O):
+        b = beta if beta > 0 else None
+        ref = (O.forward_shannon if method == "shannon" else O.forward_nfft)(fhat, x, L, m, b)
+        rec[key + "_inf"] = O.rel_err_inf(got, ref)
+        if l2:
+            rec[key + "_l2"] = O.rel_err_l2(got, ref)
+    return check
 
 
-def leg_nfft(steps, warmup, f_shannon, p_shannon):
+def leg_nfft(steps, warmup, f_shannon, p_shannon, checks: list):
     """Algorithm 2.1 on the headline workload with the same m, both beta readings; both
-    methods' error against the direct sum on truncated-domain sample nodes."""
+    methods' error against the direct sum on truncated-domain sample nodes (oracle leg)."""
     import numpy as np
 
-    import oracle as O
     import workloads as W
+    from paper_2502_07155_amd import Plan
     out = {}
     idx_all = np.sort(W.rng_for(18).choice(p_shannon.N, 2000, replace=False))
-    mask = O.in_truncated_domain(p_shannon.x[idx_all], p_shannon.L, p_shannon.m)
-    idx = idx_all[mask]
-    direct = O.direct_sum(p_shannon.fhat, p_shannon.x[idx])
-    out["shannon_vs_direct_sum"] = O.rel_err_inf(f_shannon[idx], direct)
-    for label, beta in (("nfft_beta_standard", 0.0),
-                        ("nfft_beta_shannon", O.default_beta(p_shannon.M, p_shannon.L, p_shannon.m))):
+    probe = Plan(p_shannon.d, p_shannon.M, p_shannon.L, p_shannon.m, precision="f32c")
+    beta_shannon = probe.stats()["beta"]   # the library's default beta of Algorithm 4.2
+    probe.close()
+    samples = {"shannon": f_shannon[idx_all].copy()}
+    for label, beta in (("nfft_beta_standard", 0.0), ("nfft_beta_shannon", beta_shannon)):
         p, plan, f, ms, gms, _ = run_plan(HEADLINE, "f32c", steps, warmup, "nfft", beta)
-        err, _, _ = accuracy(p, f, 5000, "nfft", beta if beta > 0 else None)
         out[label] = {"value": p.N / (ms * 1e-3), "ms_per_step": ms, "gather_ms": gms,
-                      "beta": plan.stats()["beta"], "rel_err_inf_vs_oracle": err,
-                      "rel_err_inf_vs_direct_sum": O.rel_err_inf(f[idx], direct)}
+                      "beta": plan.stats()["beta"]}
+        checks.append(accuracy_check(out[label], p, f, 5000, "nfft", beta, key="rel_err_vs_oracle"))
+        samples[label] = f[idx_all].copy()
         plan.close()
-    out["direct_sum_nodes"] = int(idx.size)
+    x, fhat, L, m = p_shannon.x[idx_all], p_shannon.fhat, p_shannon.L, p_shannon.m
+
+    def check(O):
+        mask = O.in_truncated_domain(x, L, m)
+        direct = O.direct_sum(fhat, x[mask])
+        out["shannon_vs_direct_sum"] = O.rel_err_inf(samples["shannon"][mask], direct)
+        for label in ("nfft_beta_standard", "nfft_beta_shannon"):
+            out[label]["rel_err_inf_vs_direct_sum"] = O.rel_err_inf(samples[label][mask], direct)
+        out["direct_sum_nodes"] = int(mask.sum())
+    checks.append(check)
     return out
 
 
-def leg_plan(name, prec, steps, warmup, sample=5000):
+def leg_plan(name, prec, steps, warmup, checks: list, sample=5000):
     p, plan, f, ms, gms, plan_ms = run_plan(name, prec, steps, warmup)
-    err, _, _ = accuracy(p, f, sample)
     plan.close()
-    return {"value": p.N / (ms * 1e-3), "ms_per_step": ms, "gather_ms": gms, "plan_ms": plan_ms,
-            "precision": prec, "rel_err_inf": err}
+    rec = {"value": p.N / (ms * 1e-3), "ms_per_step": ms, "gather_ms": gms, "plan_ms": plan_ms,
+           "precision": prec}
+    checks.append(accuracy_check(rec, p, f, sample))
+    return rec
 
 
-def leg_batched(steps, warmup):
+# Example 5.1 (Section 5): f(x) = sinc^2(M pi x / 2) with the triangle fhat, N = M/2
+# Chebyshev nodes (5.6), m = 5, L = 2M, error max_j |f_j - f(x_j)| (5.5).
+EXAMPLE51_M_PAPER = [20, 40, 80, 160, 320, 640, 1000]
+EXAMPLE51_M_POW2 = [16, 32, 64, 128, 256, 512, 1024]
+
+
+def example51_inputs(M: int, m: int = 5):
+    import numpy as np
+
+    import workloads as W
+    L = 2 * M
+    x = W.chebyshev_nodes(M // 2, L, m)
+    exact = np.sinc(0.5 * M * x) ** 2   # numpy's sinc is sin(pi t)/(pi t)
+    return L, x, W.triangle_fhat(M), exact
+
+
+def leg_example51(checks: list):
+    """Example 5.1 on the GPU.  Per-plan FP64 (power-of-two L: M = 16..1024) for Algorithm
+    4.2 and Algorithm 2.1 with both beta readings (the same beta as Algorithm 4.2, and the
+    standard NFFT beta); the batched FP32 path (any even L) at the paper's M = 20..1000 for
+    Algorithm 4.2.  Parity of every run with the oracle is filled in by the oracle leg."""
+    import numpy as np
+    import torch
+
+    from paper_2502_07155_amd import BatchPlan, Plan
+    m = 5
+    out = {"m": m, "per_plan_f64": {}, "batched_f32": {}}
+    for M in EXAMPLE51_M_POW2:
+        L, x, fhat, exact = example51_inputs(M, m)
+        row = {}
+        runs = (("alg4_2", "shannon", 0.0), ("alg2_1_same_beta", "nfft", None),
+                ("alg2_1_standard_beta", "nfft", 0.0))
+        beta_shannon = None
+        for label, method, beta in runs:
+            b = beta_shannon if beta is None else beta
+            plan = Plan(1, M, L, m, precision="f64", method=method, beta=b)
+            if method == "shannon":
+                beta_shannon = plan.stats()["beta"]
+            plan.set_nodes(torch.from_numpy(x[:, None]).cuda())
+            f = plan.forward(torch.from_numpy(fhat).cuda()).cpu().numpy()
+            used_beta = plan.stats()["beta"]
+            plan.close()
+            row[label] = {"max_err_vs_f": float(np.max(np.abs(f - exact))), "beta": used_beta}
+
+            def check(O, rec=row[label], f=f, x=x, fhat=fhat, L=L, method=method, beta=used_beta):
+                fn = O.forward_shannon if method == "shannon" else O.forward_nfft
+                rec["rel_err_vs_oracle"] = O.rel_err_inf(f, fn(fhat, x[:, None], L, m, beta))
+            checks.append(check)
+        out["per_plan_f64"][str(M)] = row
+    Ms = EXAMPLE51_M_PAPER
+    ins = []
+    for M in Ms:   # FP32 inputs; the exact f and the oracle see the same rounded values
+        L, x, fhat, _ = example51_inputs(M, m)
+        x = x.astype(np.float32).astype(np.float64)
+        fhat = fhat.astype(np.complex64).astype(np.complex128)
+        ins.append((L, x, fhat, np.sinc(0.5 * M * x) ** 2))
+    bp = BatchPlan(Ms, [i[0] for i in ins], [m] * len(Ms), [M // 2 for M in Ms], precision="f32")
+    bp.set_nodes(torch.from_numpy(np.concatenate([i[1] for i in ins]).astype(np.float32)).cuda())
+    fhat_all = torch.from_numpy(np.concatenate([i[2] for i in ins]).astype(np.complex64)).cuda()
+    fb = torch.empty(bp.total_N, dtype=torch.complex64, device="cuda")
+    bp.forward(fhat_all, fb)
+    fb = fb.cpu().numpy().astype(np.complex128)
+    for k, M in enumerate(Ms):
+        L, x, fhat, exact = ins[k]
+        f = fb[bp.node_offsets[k]:bp.node_offsets[k + 1]]
+        rec = {"L": L, "max_err_vs_f": float(np.max(np.abs(f - exact)))}
+        out["batched_f32"][str(M)] = rec
+
+        def check(O, rec=rec, f=f, x=x, fhat=fhat, L=L):
+            rec["rel_err_vs_oracle"] = O.rel_err_inf(f, O.forward_shannon(fhat, x[:, None], L, m))
+        checks.append(check)
+    bp.close()
+    return out
+
+
+def leg_batched(steps, warmup, checks: list):
     """512 independent d=1 instances, one graph launch per step, FP32."""
     import numpy as np
     import torch
 
-    import oracle as O
     import workloads as W
     from paper_2502_07155_amd import BatchPlan
     insts = W.batched_instances()
@@ -215,17 +309,21 @@ def leg_batched(steps, warmup):
     ms = time_calls(torch, lambda: bp.forward(fhat, out), steps, warmup, bp.stream)
     f = out.cpu().numpy().astype(np.complex128)
     rng = W.rng_for(19)
-    worst = 0.0
+    picks = []
     for i in rng.choice(len(insts), 32, replace=False):
         inst = insts[i]
         idx = rng.choice(inst.x.size, min(32, inst.x.size), replace=False)
-        ref = O.forward_shannon(inst.fhat, inst.x[idx, None], inst.L, inst.m)
-        got = f[bp.node_offsets[i]:bp.node_offsets[i + 1]][idx]
-        worst = max(worst, O.rel_err_inf(got, ref))
+        picks.append((inst, idx, f[bp.node_offsets[i]:bp.node_offsets[i + 1]][idx].copy()))
     bp.close()
-    return {"value": bp.total_N / (ms * 1e-3), "ms_per_step": ms, "plan_ms": plan_ms,
-            "instances": len(insts), "total_nodes": bp.total_N, "precision": "f32",
-            "rel_err_inf_worst_of_32_sampled_instances": worst}
+    rec = {"value": bp.total_N / (ms * 1e-3), "ms_per_step": ms, "plan_ms": plan_ms,
+           "instances": len(insts), "total_nodes": bp.total_N, "precision": "f32"}
+
+    def check(O):
+        rec["rel_err_inf_worst_of_32_sampled_instances"] = max(
+            O.rel_err_inf(got, O.forward_shannon(inst.fhat, inst.x[idx, None], inst.L, inst.m))
+            for inst, idx, got in picks)
+    checks.append(check)
+    return rec
 
 
 def leg_differentiation(steps, warmup):
@@ -251,6 +349,20 @@ def leg_differentiation(steps, warmup):
     plan.close()
     return {"value": p.N / (ms * 1e-3), "ms_per_step": ms, "precision": "f32",
             "step": "forward + backward (grad fhat, grad x)"}
+
+
+def oracle_checks(checks: list) -> None:
+    """Run the GPU legs' deferred error checks against the oracle."""
+    import oracle as O
+    for check in checks:
+        check(O)
+
+
+def oracle_leg(checks: list, name: str, nodes: int) -> dict:
+    """The oracle leg, the only part of this file that uses the oracle: the deferred error
+    checks, then the CPU baseline."""
+    oracle_checks(checks)
+    return cpu_baseline(name, nodes)
 
 
 def cpu_baseline(name: str, nodes: int):
@@ -359,8 +471,12 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    checks: list = []
     if args.leg == "batched":
-        print(json.dumps(leg_batched(args.steps, args.warmup)))
+        rec = leg_batched(args.steps, args.warmup, checks)
+        if not args.no_cpu:
+            oracle_checks(checks)
+        print(json.dumps(rec))
         return
     if args.leg == "fwd_bwd":
         print(json.dumps(leg_differentiation(args.steps, args.warmup)))
@@ -368,12 +484,20 @@ def main():
     if args.leg == "nfft":
         p, plan, f, _, _, _ = run_plan(HEADLINE, "f32c", 2, 1)
         plan.close()
-        print(json.dumps(leg_nfft(args.steps, args.warmup, f, p)))
+        rec = leg_nfft(args.steps, args.warmup, f, p, checks)
+        if not args.no_cpu:
+            oracle_checks(checks)
+        print(json.dumps(rec))
+        return
+    if args.leg == "example51":
+        rec = leg_example51(checks)
+        if not args.no_cpu:
+            oracle_checks(checks)
+        print(json.dumps(rec))
         return
 
     prec = args.precision
     p, plan, f, ms, gms, plan_ms = run_plan(args.workload, prec, args.steps, args.warmup)
-    err_inf, err_l2, _ = accuracy(p, f)
     csize, rsize = (16, 8) if prec == "f64" else (8, 4)
     ab = algorithmic_bytes(p.d, p.M, p.L, p.N, csize, rsize)
     flops = gather_flops_per_node(p.d, p.m) * p.N
@@ -397,8 +521,8 @@ def main():
         "config": {"workload": args.workload, "d": p.d, "M": p.M, "L": p.L, "m": p.m,
                    "N": p.N, "precision": prec, "method": "shannon (Algorithm 4.2)",
                    "parallelism": "single GPU"},
-        "rel_err_inf": err_inf,
-        "rel_err_l2": err_l2,
+        "rel_err_inf": None,
+        "rel_err_l2": None,
         "plan_ms": plan_ms,
         "stage_ms": {"deconv_fft": fft_ms, "gather": gms},
         "roofline": {"bound": "alu", "kernel": "k_gather (step 3 short sums)",
@@ -410,19 +534,21 @@ def main():
                 "gather_GBs": ab["gather"] / (gms * 1e-3) / 1e9, "peak_GBs": HBM_PEAK_GBS},
     }
     plan.close()
+    checks.append(accuracy_check(rec, p, f, key="rel_err", l2=True))
     if not args.headline_only and args.workload == HEADLINE and prec != "f64":
         legs = {}
         short = max(5, args.steps // 5)
-        legs["d2_M512_L1024_m5_N1M_f64"] = leg_plan(HEADLINE, "f64", short, 2)
-        legs["d2_M512_L1024_m5_N1M_nfft"] = leg_nfft(short, 2, f, p)
-        legs["d1_M256_L512_m6_N1k_f64"] = leg_plan("d1_M256_L512_m6_N1k", "f64", short, 2, 1000)
-        legs["d3_M128_L256_m4_N2M_f32c"] = leg_plan("d3_M128_L256_m4_N2M", "f32c", short, 2, 3000)
-        legs["d3_M128_L256_m4_N2M_f64"] = leg_plan("d3_M128_L256_m4_N2M", "f64", short, 2, 3000)
-        legs["batched_512_d1_f32"] = leg_batched(short, 2)
+        legs["d2_M512_L1024_m5_N1M_f64"] = leg_plan(HEADLINE, "f64", short, 2, checks)
+        legs["d2_M512_L1024_m5_N1M_nfft"] = leg_nfft(short, 2, f, p, checks)
+        legs["d1_M256_L512_m6_N1k_f64"] = leg_plan("d1_M256_L512_m6_N1k", "f64", short, 2, checks, 1000)
+        legs["d3_M128_L256_m4_N2M_f32c"] = leg_plan("d3_M128_L256_m4_N2M", "f32c", short, 2, checks, 3000)
+        legs["d3_M128_L256_m4_N2M_f64"] = leg_plan("d3_M128_L256_m4_N2M", "f64", short, 2, checks, 3000)
+        legs["batched_512_d1_f32"] = leg_batched(short, 2, checks)
         legs["d2_M256_L512_m6_N200k_fwd_bwd_f32"] = leg_differentiation(short, 2)
+        legs["example_5_1"] = leg_example51(checks)
         rec["legs"] = legs
     if not args.no_cpu and not args.headline_only:
-        rec["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_nodes)
+        rec["cpu_baseline"] = oracle_leg(checks, args.workload, args.cpu_nodes)
     print(json.dumps(rec))
 
 

@@ -1,0 +1,87 @@
+"""Example 5.1 (Section 5) on the GPU: f(x) = sinc^2(M pi x / 2), the triangle fhat, N = M/2
+Chebyshev nodes (5.6), m = 5, L = 2M, error max_j |f_j - f(x_j)| (5.5).
+
+Per-plan FP64 transforms need a power-of-two L, so that sweep runs at M = 16..1024 (the
+paper's range of 20..1000); the batched FP32 path takes any even L and runs the paper's own
+M values.  Every run is compared with the oracle on the same inputs, and the sweep must show
+the paper's outcome: both algorithms equally accurate at small M, then only Algorithm 4.2
+keeps improving when Algorithm 2.1 uses the same beta."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "example_5_1.json")
+M_POW2 = [16, 32, 64, 128, 256, 512, 1024]
+
+
+def _inputs(M, m):
+    L = 2 * M
+    x = W.chebyshev_nodes(M // 2, L, m)
+    return L, x, W.triangle_fhat(M), O.example51_f(x, M)
+
+
+def _plan_forward(M, L, m, x, fhat, method, beta):
+    import torch
+    from paper_2502_07155_amd import Plan
+    plan = Plan(1, M, L, m, precision="f64", method=method, beta=beta)
+    plan.set_nodes(torch.from_numpy(x[:, None]).cuda())
+    f = plan.forward(torch.from_numpy(fhat).cuda()).cpu().numpy()
+    used = plan.stats()["beta"]
+    plan.close()
+    return f, used
+
+
+def test_example51_per_plan_sweep():
+    m = json.load(open(GOLDEN))["m"]
+    err = {}
+    for M in M_POW2:
+        L, x, fhat, exact = _inputs(M, m)
+        f42, beta42 = _plan_forward(M, L, m, x, fhat, "shannon", 0.0)
+        f21, _ = _plan_forward(M, L, m, x, fhat, "nfft", beta42)
+        f21s, beta_std = _plan_forward(M, L, m, x, fhat, "nfft", 0.0)
+        assert beta42 == pytest.approx(O.default_beta(M, L, m), rel=1e-15)
+        assert beta_std == pytest.approx(O.default_beta(M, L, m, "nfft"), rel=1e-15)
+        assert O.rel_err_inf(f42, O.forward_shannon(fhat, x[:, None], L, m, beta42)) <= 1e-12
+        assert O.rel_err_inf(f21, O.forward_nfft(fhat, x[:, None], L, m, beta42)) <= 1e-12
+        assert O.rel_err_inf(f21s, O.forward_nfft(fhat, x[:, None], L, m, beta_std)) <= 1e-12
+        err[M] = tuple(float(np.max(np.abs(f - exact))) for f in (f42, f21, f21s))
+        print(f"M={M}: alg 4.2 {err[M][0]:.2e}, alg 2.1 same beta {err[M][1]:.2e}, "
+              f"alg 2.1 standard beta {err[M][2]:.2e}")
+    for M in (16, 32, 64):
+        assert err[M][1] / err[M][0] < 1.2          # equal at small M
+    assert err[1024][0] < err[16][0] / 300          # Algorithm 4.2 keeps improving
+    assert err[1024][1] > 0.5 * err[128][1]         # Algorithm 2.1 (same beta) stalls
+    for M in (256, 512, 1024):
+        assert err[M][0] < err[M][1] / 2
+        assert err[M][2] < 2 * err[M][0]            # with the standard beta it does not stall
+
+
+def test_example51_batched_at_the_papers_M():
+    import torch
+    from paper_2502_07155_amd import BatchPlan
+    g = json.load(open(GOLDEN))
+    m, Ms = g["m"], g["M_values"]
+    ins = [_inputs(M, m) for M in Ms]
+    bp = BatchPlan(Ms, [i[0] for i in ins], [m] * len(Ms), [M // 2 for M in Ms], precision="f32")
+    xs = [i[1].astype(np.float32) for i in ins]
+    bp.set_nodes(torch.from_numpy(np.concatenate(xs)).cuda())
+    fh = [i[2].astype(np.complex64) for i in ins]
+    f = bp.forward(torch.from_numpy(np.concatenate(fh)).cuda()).cpu().numpy().astype(np.complex128)
+    bp.close()
+    err = {}
+    for k, M in enumerate(Ms):
+        L = ins[k][0]
+        x = xs[k].astype(np.float64)
+        got = f[bp.node_offsets[k]:bp.node_offsets[k + 1]]
+        ref = O.forward_shannon(fh[k].astype(np.complex128), x[:, None], L, m)
+        assert O.rel_err_inf(got, ref) <= 1e-5, M
+        err[M] = float(np.max(np.abs(got - O.example51_f(x, M))))
+        print(f"M={M} (L={L}): alg 4.2 FP32 {err[M]:.2e}")
+    assert err[1000] < err[20] / 300
