@@ -556,6 +556,38 @@ def dirichlet(x: np.ndarray, M: int) -> np.ndarray:
     return out
 
 
+# ---------------------------------------------------------------------------
+# Section 5, Figure 5.1: approximations of e^{2 pi i v x} at a real frequency v (d = 1)
+# ---------------------------------------------------------------------------
+
+def exp_samples(v: float, L: int) -> np.ndarray:
+    """e^{2 pi i v l / L} for l in I_L, centred order (index l + L/2)."""
+    ell = band(L).astype(np.float64)
+    return np.exp(2j * np.pi * v * ell / L)
+
+
+def exp_approx_nfft(v: float, x: np.ndarray, L: int, m: int, beta: float,
+                    win: str = "sinh") -> np.ndarray:
+    """Right-hand side of (5.1): (1 / (L phihat(v))) sum_{l in I_L} e^{2 pi i v l/L}
+    phi~(x - l/L), the 1-periodic window sum of Algorithm 2.1 at a real v."""
+    g = exp_samples(v, L) / (L * phihat1(v, L, m, beta, win)[0])
+    return gather_nfft(g, np.asarray(x, dtype=np.float64).reshape(-1, 1), L, m, beta, win)
+
+
+def exp_approx_shannon(v: float, x: np.ndarray, L: int, m: int, beta: float,
+                       win: str = "sinh") -> np.ndarray:
+    """Right-hand side of (5.2): sum_{l in I_L} e^{2 pi i v l/L} psi(x - l/L), the
+    regularized Shannon sum without the deconvolution (l outside I_L contributes 0)."""
+    return gather_shannon(exp_samples(v, L), np.asarray(x, dtype=np.float64).reshape(-1, 1),
+                          L, m, beta, win)
+
+
+def fig51_frequencies(M: int, m: int, S: int) -> np.ndarray:
+    """v_s = -M/2 - m + s/S, s = 0..S(M + 2m)  (5.4)."""
+    s = np.arange(S * (M + 2 * m) + 1, dtype=np.float64)
+    return -M / 2 - m + s / S
+
+
 def example51_f(x: np.ndarray, M: int) -> np.ndarray:
     """Example 5.1 target f(x) = sinc^2(M pi x / 2)."""
     return sinc_pi(0.5 * M * np.asarray(x, dtype=np.float64)) ** 2

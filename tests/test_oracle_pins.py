@@ -442,3 +442,60 @@ def test_dpsi_matches_difference_quotient():
     fd = (O.psi_g(t + h, m, beta) - O.psi_g(t - h, m, beta)) / (2 * h)
     assert np.max(np.abs(O.dpsi_g(t, m, beta) - fd)) < 1e-7
     assert np.all(O.dpsi_g(np.array([-m, m, m + 1.0]), m, beta) == 0.0)
+
+
+# ---------------------------------------------------------------- Figure 5.1
+
+def test_exponential_approximations_at_integer_frequencies_equal_the_transforms():
+    """At an integer v = k in I_M the right-hand side of (5.1) is Algorithm 2.1 applied to
+    the unit coefficient vector e_k, and that of (5.2) is Algorithm 4.2 applied to e_k times
+    L psihat(k) (the deconvolution (5.2) leaves out): an explicit-exponential path against
+    the FFT path."""
+    M, L, m = 20, 40, 5
+    x = np.linspace(-0.5 + m / L, 0.5 - m / L, 301)[:-1, None]
+    b = O.default_beta(M, L, m)
+    for k in (-10, -3, 0, 7, 9):
+        e = np.zeros(M, dtype=np.complex128)
+        e[k + M // 2] = 1.0
+        nf = O.forward_nfft(e, x, L, m, b)
+        assert np.max(np.abs(O.exp_approx_nfft(float(k), x[:, 0], L, m, b) - nf)) <= 1e-13 * np.max(np.abs(nf))
+        sh = O.forward_shannon(e, x, L, m, b) * L * O.psihat1(float(k), L, m, b)[0]
+        assert np.max(np.abs(O.exp_approx_shannon(float(k), x[:, 0], L, m, b) - sh)) <= 1e-13 * np.max(np.abs(sh))
+
+
+def _fig51_errors(x, L, m, vs, beta_nfft):
+    M = 20
+    b = O.default_beta(M, L, m)
+    e_sh, e_nf = [], []
+    for v in vs:
+        ex = np.exp(2j * np.pi * v * x)
+        e_sh.append(np.max(np.abs(ex - O.exp_approx_shannon(v, x, L, m, b))))
+        e_nf.append(np.max(np.abs(ex - O.exp_approx_nfft(v, x, L, m, beta_nfft))))
+    return np.array(e_sh), np.array(e_nf)
+
+
+def test_figure_5_1_qualitative_outcome():
+    """Figure 5.1's statements (coarse grid: S = 4, 2000 points): on [-1/2, 1/2) the sum
+    (5.2) fails everywhere and (5.1) works only at integer v; on the truncated interval both
+    work for |v| <= M/2 and fail beyond, (5.2) with the smaller error when both use the same
+    beta.  With the standard NFFT beta, (5.1) beats (5.2) instead (reading A1)."""
+    g = json.load(open(os.path.join(GOLDEN, "figure_5_1.json")))
+    M, L, m = g["M"], g["L"], g["m"]
+    vs = O.fig51_frequencies(M, m, 4)
+    inband = np.abs(vs) <= M / 2
+    integer = np.abs(vs - np.rint(vs)) < 1e-12
+    P = 2000
+    full = -0.5 + np.arange(P) / P
+    a, b = -0.5 + m / L, 0.5 - m / L
+    trunc = a + np.arange(P) * (b - a) / P
+    same = O.default_beta(M, L, m)
+    sh, nf = _fig51_errors(full, L, m, vs, same)
+    assert sh.min() > 0.5
+    assert nf[inband & integer].max() < 0.02 and nf[inband & ~integer].max() > 1.0
+    sh, nf = _fig51_errors(trunc, L, m, vs, same)
+    assert sh[inband].max() < 1e-3 and nf[inband].max() < 2e-2
+    assert sh[np.abs(vs) >= M / 2 + 1].min() > 5 * sh[inband].max()   # grows beyond the band
+    assert sh[np.abs(vs) >= M / 2 + m - 1e-9].min() > 0.1
+    assert sh[inband].max() < nf[inband].max() / 5
+    _, nf_std = _fig51_errors(trunc, L, m, vs[inband], O.default_beta(M, L, m, "nfft"))
+    assert nf_std.max() < sh[inband].max() / 100
