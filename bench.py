@@ -51,9 +51,10 @@ def parse():
                     help="skip the oracle leg (CPU baseline and the error checks against the oracle)")
     ap.add_argument("--cpu-nodes", type=int, default=1_000_000,
                     help="nodes of the oracle's step-3 sample for the CPU baseline")
-    ap.add_argument("--leg", choices=["batched", "fwd_bwd", "nfft", "example51"],
+    ap.add_argument("--leg", choices=["batched", "fwd_bwd", "nfft", "example51", "fig51"],
                     help="run only this leg (batched d=1 instances, d=2 forward + backward, "
-                         "Algorithm 2.1 on the headline workload, or the Example 5.1 sweep) "
+                         "Algorithm 2.1 on the headline workload, the Example 5.1 sweep or the "
+                         "Figure 5.1 sweep) "
                          "and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (for counter scaling)")
@@ -288,6 +289,75 @@ def leg_example51(checks: list):
     return out
 
 
+def leg_fig51(checks: list):
+    """Figure 5.1 (Section 5): e(v) = max_p |e^{2 pi i v x_p} - h(x_p)| (5.3) at P = 1e5
+    equispaced x_p, for v_s of (5.4) with S = 32, M = 20, L = 40, m = 5 (sinh window), on
+    [-1/2, 1/2) and on the truncated interval.  h is (5.2), the short sums of Algorithm 4.2
+    on the samples e^{2 pi i v l/L}, or (5.1), the periodic window sums of Algorithm 2.1 on
+    those samples divided by L phihat(v), with the same beta and with the standard one.
+    Every h is one bl_interpolate call of an FP64 plan (L = 40 needs no FFT)."""
+    import numpy as np
+    import torch
+
+    from paper_2502_07155_amd import Plan, window_transform
+    M, L, m, S, P = 20, 40, 5, 32, 100_000
+    vs = -M / 2 - m + np.arange(S * (M + 2 * m) + 1) / S
+    inband = np.abs(vs) <= M / 2
+    integer = np.abs(vs - np.rint(vs)) < 1e-12
+    ell = np.arange(L) - L // 2
+    a, b = -0.5 + m / L, 0.5 - m / L
+    intervals = {"full": -0.5 + np.arange(P) / P, "truncated": a + np.arange(P) * (b - a) / P}
+    v_pick = set(range(0, vs.size, 37))         # parity sample: every 37th frequency
+    out = {"M": M, "L": L, "m": m, "S": S, "P": P, "frequencies": int(vs.size)}
+    t_all = time.perf_counter()
+    calls = 0
+    for iname, x in intervals.items():
+        xd = torch.from_numpy(x[:, None]).cuda()
+        node_pick = np.sort(np.random.default_rng(51).choice(P, 2000, replace=False))
+        for label, method, beta_arg in (("eq5_2_alg4_2", "shannon", 0.0),
+                                        ("eq5_1_alg2_1_same_beta", "nfft", None),
+                                        ("eq5_1_alg2_1_standard_beta", "nfft", 0.0)):
+            if beta_arg is None:
+                probe = Plan(1, M, L, m, precision="f64")
+                beta_arg = probe.stats()["beta"]
+                probe.close()
+            plan = Plan(1, M, L, m, precision="f64", method=method, beta=beta_arg)
+            plan.set_nodes(xd)
+            beta = plan.stats()["beta"]
+            fac = np.ones(vs.size)
+            if method == "nfft":
+                fac = 1.0 / (L * window_transform(vs, M, L, m, beta, "sinh", "nfft"))
+            theta = torch.from_numpy(np.exp(2j * np.pi * np.outer(vs, ell) / L) * fac[:, None]).cuda()
+            h = torch.empty(P, dtype=torch.complex128, device="cuda")
+            err = np.empty(vs.size)
+            picked = {}
+            for i, v in enumerate(vs):
+                plan.interpolate(theta[i], out=h)
+                calls += 1
+                e = (h - torch.exp(2j * np.pi * v * xd[:, 0])).abs().max()
+                err[i] = float(e)
+                if i in v_pick:
+                    picked[i] = h[torch.from_numpy(node_pick).cuda()].cpu().numpy()
+            plan.close()
+            rec = {"beta": beta,
+                   "max_e_in_band": float(err[inband].max()),
+                   "max_e_in_band_integer_v": float(err[inband & integer].max()),
+                   "max_e_in_band_noninteger_v": float(err[inband & ~integer].max()),
+                   "min_e_beyond_band_plus_1": float(err[np.abs(vs) >= M / 2 + 1].min()),
+                   "e_at_v": {f"{vs[i]:g}": float(err[i]) for i in range(0, vs.size, S * 5)}}
+            out[f"{iname}/{label}"] = rec
+
+            def check(O, rec=rec, picked=picked, x=x[node_pick], method=method, beta=beta):
+                fn = O.exp_approx_shannon if method == "shannon" else O.exp_approx_nfft
+                rec["rel_err_vs_oracle"] = max(O.rel_err_inf(hv, fn(vs[i], x, L, m, beta))
+                                               for i, hv in picked.items())
+            checks.append(check)
+    torch.cuda.synchronize()
+    out["seconds"] = time.perf_counter() - t_all
+    out["interpolate_calls"] = calls
+    return out
+
+
 def leg_batched(steps, warmup, checks: list):
     """512 independent d=1 instances, one graph launch per step, FP32."""
     import numpy as np
@@ -489,6 +559,12 @@ def main():
             oracle_checks(checks)
         print(json.dumps(rec))
         return
+    if args.leg == "fig51":
+        rec = leg_fig51(checks)
+        if not args.no_cpu:
+            oracle_checks(checks)
+        print(json.dumps(rec))
+        return
     if args.leg == "example51":
         rec = leg_example51(checks)
         if not args.no_cpu:
@@ -546,6 +622,7 @@ def main():
         legs["batched_512_d1_f32"] = leg_batched(short, 2, checks)
         legs["d2_M256_L512_m6_N200k_fwd_bwd_f32"] = leg_differentiation(short, 2)
         legs["example_5_1"] = leg_example51(checks)
+        legs["figure_5_1"] = leg_fig51(checks)
         rec["legs"] = legs
     if not args.no_cpu and not args.headline_only:
         rec["cpu_baseline"] = oracle_leg(checks, args.workload, args.cpu_nodes)

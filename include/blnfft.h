@@ -83,7 +83,9 @@ typedef struct {
  * step 0a (phihat(k)) is computed here on the host in double precision.
  *   d      : 1, 2 or 3.
  *   M      : bandwidth per dimension, even, >= 2 (I_M, Section 1).
- *   L      : oversampled grid per dimension, even, L >= M (Algorithm 4.2, L = M(1+lambda)).
+ *   L      : oversampled grid per dimension, even, L >= M (Algorithm 4.2, L = M(1+lambda)),
+ *            L <= 8192.  bl_forward and bl_adjoint need a power of two L >= 16 (their FFT);
+ *            any even L gives a plan whose short sums (bl_interpolate) run.
  *   m      : truncation, 1 <= m and 2m < L; this build's kernels take 2 <= m <= 8
  *            (BL_EUNSUPPORTED otherwise).
  *   win    : window: BL_WIN_SINH (eq. (3.4)) or BL_WIN_CKB (continuous Kaiser-Bessel,
@@ -116,11 +118,13 @@ bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev);
  *   step 3: f_j = sum_{l in J_{L,m}(x_j)} theta_l psi(x_j - l/L)           (4.8),
  * with theta_l = 0 for l outside I_L (zero-extended sum; BL_NFFT wraps periodically).
  *   fhat_dev : M^d complex (input).   f_dev : N complex (output, overwritten).
- * Asynchronous.  Keeps theta for bl_grad_x / bl_get_theta. */
+ * Asynchronous.  Keeps theta for bl_grad_x / bl_get_theta.  BL_EUNSUPPORTED unless L is a
+ * power of two >= 16. */
 bl_status bl_forward(bl_plan plan, const void* fhat_dev, void* f_dev);
 
 /* Regularized Shannon sampling formula (3.5) truncated to I_L: evaluate step 3 alone on
- * given samples theta_dev (L^d complex, centred order) at the bound nodes.
+ * given samples theta_dev (L^d complex, centred order) at the bound nodes (BL_NFFT: the
+ * periodic window sums of Algorithm 2.1 on those samples).  Any even L.
  *   f_dev : N complex (output).  Asynchronous. */
 bl_status bl_interpolate(bl_plan plan, const void* theta_dev, void* f_dev);
 
@@ -131,7 +135,7 @@ bl_status bl_get_theta(bl_plan plan, void* theta_dev);
 /* Adjoint of the factorisation (4.11): fhat_out = D_psihat^H F^H Psi^T g  (BL_SHANNON), or
  * D^H F^H B^T g (BL_NFFT).  D is real; F^H uses e^{-2 pi i k l / L}.
  *   g_dev : N complex (input).   fhat_dev : M^d complex (output, overwritten).
- * Asynchronous. */
+ * Asynchronous.  BL_EUNSUPPORTED unless L is a power of two >= 16. */
 bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev);
 
 /* Gradient with respect to the nodes: gx[j*d + t] = Re( conj(g_j) * d f_j / d x_jt ),

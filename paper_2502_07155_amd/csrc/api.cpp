@@ -220,9 +220,10 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     if (std::isnan(beta) || std::isinf(beta)) return fail(BL_EINVAL, "beta not finite");
     if (m < kMinM || m > kMaxM)
         return fail(BL_EUNSUPPORTED, "compiled short-sum kernels cover 2 <= m <= 8");
+    // The per-plan FFT needs a power of two L >= 16; other even L give plans whose short sums
+    // (bl_interpolate) run, while bl_forward and bl_adjoint report BL_EUNSUPPORTED.
     FftFactors fac16, fac4;
-    if (L > (1 << 30) || !factor_length(int(L), 16, &fac16) || !factor_length(int(L), 4, &fac4))
-        return fail(BL_EUNSUPPORTED, "per-plan FFT needs L a power of two, L >= 16");
+    const bool fft_ok = L <= (1 << 30) && factor_length(int(L), 16, &fac16) && factor_length(int(L), 4, &fac4);
     // one line of L complex values per LDS pass with <= 512 threads of 16 values each
     const int64_t Lmax = 8192;
     if (L > Lmax) return fail(BL_EUNSUPPORTED, "L above the LDS FFT limit for this precision");
@@ -238,6 +239,7 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     p.m = m;
     p.win = win;
     p.method = method;
+    p.fft_ok = fft_ok;
     p.prec = prec;
     p.beta = (beta > 0.0) ? beta : default_beta(M, L, m, method);
     p.stream = static_cast<hipStream_t>(stream);
@@ -264,13 +266,13 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     const FftFactors* facs[2] = {&fac16, &fac4};
     FftStages* sts[2] = {&p.st16, &p.st4};
     for (int v = 0; v < 2; ++v) {
-        stage_twiddles(*facs[v], tw0, &tw[v], sts[v]->tw_off);
+        if (fft_ok) stage_twiddles(*facs[v], tw0, &tw[v], sts[v]->tw_off);
         if (tw[v].empty()) tw[v].assign(2, 0.0);
         sts[v]->tw_len = int(tw[v].size() / 2);
         sts[v]->nmain = 0;
         sts[v]->rlast = 1;
         const int E = v == 0 ? 16 : 4;
-        for (int s = 0; s < facs[v]->nstages; ++s) {
+        for (int s = 0; fft_ok && s < facs[v]->nstages; ++s) {
             if (facs[v]->radix[s] == E) ++sts[v]->nmain;
             else sts[v]->rlast = facs[v]->radix[s];
         }
@@ -374,6 +376,7 @@ bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev) {
 bl_status bl_forward(bl_plan plan, const void* fhat_dev, void* f_dev) {
     BL_TRY(check_plan(plan));
     Plan& p = plan->p;
+    if (!p.fft_ok) return fail(BL_EUNSUPPORTED, "bl_forward needs L a power of two, L >= 16 (bl_interpolate takes any even L)");
     if (!p.have_nodes) return fail(BL_ESTATE, "bl_set_nodes must succeed before bl_forward");
     if (!fhat_dev || (p.N > 0 && !f_dev)) return fail(BL_EINVAL, "NULL buffer");
     if (p.use_graph) {
@@ -408,6 +411,7 @@ bl_status bl_get_theta(bl_plan plan, void* theta_dev) {
 bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev) {
     BL_TRY(check_plan(plan));
     Plan& p = plan->p;
+    if (!p.fft_ok) return fail(BL_EUNSUPPORTED, "bl_adjoint needs L a power of two, L >= 16");
     if (!p.have_nodes) return fail(BL_ESTATE, "bl_set_nodes must succeed before bl_adjoint");
     if (!fhat_dev || (p.N > 0 && !g_dev)) return fail(BL_EINVAL, "NULL buffer");
     if (!p.d_sgrid) {

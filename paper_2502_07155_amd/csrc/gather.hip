@@ -303,7 +303,10 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
                     li += ct * S[t];
                     int p = n0[t] - m + 1 + ct;   // cell index of this grid point
                     if (METHOD == 1) {
-                        p &= L - 1;               // periodic; L is a power of two
+                        // periodic: p lies in [-m, 2L + m) (tile start < L, tile <= L, m < L)
+                        p += p < 0 ? L : 0;
+                        p -= p >= L ? L : 0;
+                        p -= p >= L ? L : 0;
                     } else if (p < 0 || p >= L) {
                         ingrid = false;
                     }

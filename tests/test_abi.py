@@ -68,7 +68,7 @@ def _create(lib, d=2, M=64, L=128, m=5, win=0, beta=0.0, method=0, prec=2):
     (dict(d=0), 1), (dict(d=4), 1), (dict(M=63), 1), (dict(M=0), 1), (dict(L=127), 1),
     (dict(L=32, M=64), 1), (dict(m=0), 1), (dict(m=64), 1), (dict(win=7), 1),
     (dict(method=3), 1), (dict(prec=9), 1), (dict(beta=float("nan")), 1),
-    (dict(m=9, L=256), 6), (dict(L=16384), 6), (dict(L=96, M=64), 6),
+    (dict(m=9, L=256), 6), (dict(L=16384), 6), (dict(d=3, L=2048, M=64), 6),
 ])
 def test_plan_create_rejects_before_device_use(lib, kw, status):
     st, h = _create(lib, **kw)

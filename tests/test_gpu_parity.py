@@ -104,6 +104,25 @@ def test_interpolate_on_given_samples(d, M, L, m, N, prec):
     assert O.rel_err_inf(f, fo) <= TOL[prec]
 
 
+@pytest.mark.parametrize("d,M,L,m,N", [(1, 20, 40, 5, 3000), (1, 100, 200, 8, 2000),
+                                       (2, 24, 48, 4, 4000), (3, 10, 20, 3, 2000)])
+@pytest.mark.parametrize("method", ["shannon", "nfft"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_interpolate_any_even_L(d, M, L, m, N, method, prec):
+    """Step 3 alone for L not a power of two (no FFT involved): both methods, several tiles
+    per dimension with a partial last tile, so periodic indices wrap across tile edges."""
+    p = W.custom_problem(d, M, L, m, N, seed=90 + d + L, precision="f32" if prec != "f64" else "f64")
+    theta = W.complex_normal(W.rng_for(91), (L,) * d)
+    if prec != "f64":
+        theta = theta.astype(np.complex64).astype(np.complex128)
+    plan = make_plan(p, prec, method)
+    plan.set_nodes(dev_real(p.x, prec))
+    f = host(plan.interpolate(dev_cplx(theta, prec)))
+    beta = O.default_beta(M, L, m, method)
+    fo = (O.gather_shannon if method == "shannon" else O.gather_nfft)(theta, p.x, L, m, beta)
+    assert O.rel_err_inf(f, fo) <= TOL[prec]
+
+
 FULL = [
     ("d1_M256_L512_m6_N1k", "f64"),
     ("d1_M256_L512_m6_N1k", "f32c"),
