@@ -358,6 +358,39 @@ def leg_fig51(checks: list):
     return out
 
 
+def leg_precomputed_weights(steps, warmup, checks: list):
+    """Algorithm 4.2 step 0b with stored weights on the headline workload (FP32C): the
+    d x 2m weights of every node are read from HBM by the short sums instead of being
+    evaluated.  Reports both short-sum times, the one-time weight pass and the bytes."""
+    import torch
+
+    import workloads as W
+    from paper_2502_07155_amd import Plan
+    p = W.make_problem(HEADLINE, precision="f32")
+    x = torch.from_numpy(p.x).to(torch.float32).cuda()
+    fhat = torch.from_numpy(p.fhat).to(torch.complex64).cuda()
+    plan = Plan(p.d, p.M, p.L, p.m, precision="f32c")
+    plan.set_nodes(x)
+    out = torch.empty(p.N, dtype=torch.complex64, device="cuda")
+    plan.forward(fhat, out=out)
+    theta = plan.theta()
+    g_fly = time_calls(torch, lambda: plan.interpolate(theta, out=out), steps, warmup, plan.stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.precompute_weights(True)
+    torch.cuda.synchronize()
+    pre_ms = (time.perf_counter() - t0) * 1e3
+    ms = time_calls(torch, lambda: plan.forward(fhat, out=out), steps, warmup, plan.stream)
+    g_pre = time_calls(torch, lambda: plan.interpolate(theta, out=out), steps, warmup, plan.stream)
+    f = out.cpu().numpy().astype("complex128")
+    plan.close()
+    rec = {"value": p.N / (ms * 1e-3), "ms_per_step": ms, "gather_ms_precomputed": g_pre,
+           "gather_ms_on_the_fly": g_fly, "precompute_ms": pre_ms,
+           "weight_bytes": p.N * p.d * 2 * p.m * 4, "precision": "f32c"}
+    checks.append(accuracy_check(rec, p, f, 5000))
+    return rec
+
+
 def leg_batched(steps, warmup, checks: list):
     """512 independent d=1 instances, one graph launch per step, FP32."""
     import numpy as np
@@ -621,6 +654,7 @@ def main():
         legs["d3_M128_L256_m4_N2M_f64"] = leg_plan("d3_M128_L256_m4_N2M", "f64", short, 2, checks, 3000)
         legs["batched_512_d1_f32"] = leg_batched(short, 2, checks)
         legs["d2_M256_L512_m6_N200k_fwd_bwd_f32"] = leg_differentiation(short, 2)
+        legs["d2_M512_L1024_m5_N1M_precomputed_weights"] = leg_precomputed_weights(short, 2, checks)
         legs["example_5_1"] = leg_example51(checks)
         legs["figure_5_1"] = leg_fig51(checks)
         rec["legs"] = legs

@@ -112,6 +112,16 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
  * infinite or outside [-1/2, 1/2) (the plan then holds no nodes). */
 bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev);
 
+/* Algorithm 4.2 step 0b in precomputed form: evaluate the d x 2m window weights
+ * psi(x_jt - l_t / L) of every bound node once and keep them in plan workspace
+ * (N * d * 2m values of the plan's real type), so that later bl_forward and bl_interpolate
+ * calls read them instead of evaluating them (for repeated transforms with fixed nodes).
+ *   enable : nonzero to compute and use them, 0 to free them and evaluate on the fly again.
+ * BL_ESTATE without bound nodes, BL_EUNSUPPORTED for BL_NFFT plans.  The next
+ * bl_set_nodes discards them.  Results equal the on-the-fly ones (same weight arithmetic).
+ * Synchronous. */
+bl_status bl_precompute_weights(bl_plan plan, int enable);
+
 /* Forward transform, Algorithm 4.2 steps 1-3 (or Algorithm 2.1 steps 1-3):
  *   step 1: thetahat(k) = fhat(k) / psihat(k) on I_M, 0 on I_L \ I_M;
  *   step 2: theta_l = L^-d sum_{k in I_L} thetahat(k) e^{2 pi i k l / L}   (4.7);

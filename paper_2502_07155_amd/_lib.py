@@ -17,7 +17,8 @@ METHODS = {"shannon": 0, "nfft": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "f32c": 2}
 
 EXPORTS = [
-    "bl_plan_create", "bl_set_nodes", "bl_forward", "bl_interpolate", "bl_get_theta",
+    "bl_plan_create", "bl_set_nodes", "bl_precompute_weights", "bl_forward", "bl_interpolate",
+    "bl_get_theta",
     "bl_adjoint", "bl_grad_x", "bl_plan_stats", "bl_plan_destroy", "bl_window_transform",
     "bl_batch_create", "bl_batch_set_nodes", "bl_batch_forward", "bl_batch_destroy",
     "bl_status_string", "bl_last_error", "bl_version",
@@ -59,6 +60,7 @@ def load() -> ctypes.CDLL:
     sig = {
         "bl_plan_create": [P(vp), i32, i64, i64, i32, i32, dbl, i32, i32, vp],
         "bl_set_nodes": [vp, i64, vp],
+        "bl_precompute_weights": [vp, i32],
         "bl_forward": [vp, vp, vp],
         "bl_interpolate": [vp, vp, vp],
         "bl_get_theta": [vp, vp],

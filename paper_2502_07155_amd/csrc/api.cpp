@@ -92,6 +92,9 @@ void free_plan(Plan& p) {
     hipFree(p.d_tile_cursor);
     hipFree(p.d_chunk_offset);
     hipFree(p.d_flags);
+    hipFree(p.d_wpre);
+    p.d_wpre = nullptr;
+    p.use_wpre = false;
 }
 
 // Tile edge per dimension for the short-sum kernels: the staged tile plus halo must fit
@@ -352,6 +355,12 @@ bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev) {
     p.have_theta = false;
     p.N = 0;
     drop_graph(p);
+    if (p.d_wpre) {   // precomputed weights belong to the previous nodes
+        BL_HIP(hipStreamSynchronize(p.stream));
+        hipFree(p.d_wpre);
+        p.d_wpre = nullptr;
+    }
+    p.use_wpre = false;
     const int64_t chunk_bound = N / p.chunk_cap + p.ntiles + 1;
     if (N > p.N_cap || chunk_bound > p.chunk_alloc) {
         BL_HIP(hipStreamSynchronize(p.stream));
@@ -387,6 +396,34 @@ bl_status bl_forward(bl_plan plan, const void* fhat_dev, void* f_dev) {
         BL_TRY(forward_launches(p, fhat_dev, f_dev));
     }
     p.have_theta = true;
+    return BL_OK;
+}
+
+bl_status bl_precompute_weights(bl_plan plan, int enable) {
+    BL_TRY(check_plan(plan));
+    Plan& p = plan->p;
+    drop_graph(p);   // the short-sum kernel changes
+    if (!enable) {
+        BL_HIP(hipStreamSynchronize(p.stream));
+        hipFree(p.d_wpre);
+        p.d_wpre = nullptr;
+        p.use_wpre = false;
+        return BL_OK;
+    }
+    if (p.method != BL_SHANNON) return fail(BL_EUNSUPPORTED, "precomputed weights are implemented for BL_SHANNON");
+    if (!p.have_nodes) return fail(BL_ESTATE, "bl_set_nodes must succeed before bl_precompute_weights");
+    if (p.use_wpre) return BL_OK;
+    const size_t bytes = size_t(std::max<int64_t>(p.N, 1)) * size_t(p.d) * size_t(2 * p.m) * p.real_size();
+    size_t extra = 0;
+    BL_TRY(dev_alloc(&p.d_wpre, bytes, &extra));
+    const bl_status s = launch_weights(p);
+    if (s != BL_OK) {
+        hipFree(p.d_wpre);
+        p.d_wpre = nullptr;
+        return s;
+    }
+    BL_HIP(hipStreamSynchronize(p.stream));
+    p.use_wpre = true;
     return BL_OK;
 }
 

@@ -97,7 +97,9 @@ struct Plan {
     double poly64_err = 0.0;
     bool use_poly64 = false;
     double edge_k = 1.0;
-    bool fft_ok = true;            // L is a power of two >= 16: steps 1-2 (and the adjoint) available           // edge exponent of the weight polynomials (edge_exponent)
+    bool fft_ok = true;
+    void* d_wpre = nullptr;        // precomputed weights (bl_precompute_weights), binned order
+    bool use_wpre = false;            // L is a power of two >= 16: steps 1-2 (and the adjoint) available           // edge exponent of the weight polynomials (edge_exponent)
     // Inverse-direction twiddles for the adjoint are the conjugates; computed in kernel.
 
     // FFT ping-pong buffers and the grid of theta (L^d complex).
@@ -181,6 +183,8 @@ bl_status launch_forward_fft(Plan& p, const void* fhat);
 bl_status launch_adjoint_fft(Plan& p, const void* grid, void* fhat_out);
 // Step 3 on the plan's grid (or a given theta).
 bl_status launch_gather(Plan& p, const void* theta, void* f);
+// Evaluate the weights of every bound node into p.d_wpre (Algorithm 4.2, step 0b).
+bl_status launch_weights(Plan& p);
 // Binning of nodes.
 bl_status launch_binning(Plan& p, const void* x, int64_t N);
 // Adjoint spreading Psi^T g (or B^T g) onto `grid` (L^d, centred), which it overwrites.

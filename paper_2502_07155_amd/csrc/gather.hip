@@ -225,9 +225,50 @@ struct GatherArgs {
     alignas(16) double poly64[kMaxM * kPolyCoef64];   // double ones (see weights_poly64)
     int use_poly64;
     float edge_k;   // edge exponent of the weight polynomials
+    const void* wpre;   // PRE: weights of node j (binned order) at [j][t][o], d x 2m each
+    int64_t N;          // k_weights: bound nodes
 };
 
-template <typename R, int D, int M2, int ACC, int METHOD>
+// Weights of node j (binned order), per dimension, as the short-sum kernel evaluates them.
+template <typename R, int D, int M2, int METHOD>
+__device__ __forceinline__ void node_weights(const GatherArgs& a, const R* theta, const float* coef,
+                                             const double* coef64, R (*w)[M2]) {
+    constexpr int m = M2 / 2;
+    if constexpr (std::is_same<R, float>::value) {
+        weights_poly<D, M2, kPolyCoef>(theta, coef, w, a.edge_k);
+    } else if (a.use_poly64) {
+        weights_poly64<D, M2, kPolyCoef64>(theta, coef64, w, double(a.edge_k));
+    } else {
+#pragma unroll
+        for (int t = 0; t < D; ++t)
+            weights<R, M2, METHOD>(theta[t], R(a.beta), R(a.cb), R(1) / R(m * m), w[t]);
+    }
+}
+
+// Algorithm 4.2, step 0b in precomputed form: the d x 2m weights of every bound node,
+// stored in binned order for the PRE short-sum kernels (one thread per node).
+template <typename R, int D, int M2>
+__global__ void __launch_bounds__(256) k_weights(GatherArgs a) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= a.N) return;
+    const R* __restrict__ xs = static_cast<const R*>(a.xs);
+    R theta[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        int n;
+        cell_of<R>(xs[j * D + t], a.L, n, theta[t]);
+    }
+    R w[D][M2];
+    node_weights<R, D, M2, 0>(a, theta, a.poly, a.poly64, w);
+    R* __restrict__ out = static_cast<R*>(const_cast<void*>(a.wpre)) + j * (D * M2);
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+#pragma unroll
+        for (int o = 0; o < M2; ++o) out[t * M2 + o] = w[t][o];
+}
+
+// PRE: the weights come from a.wpre (bl_precompute_weights) instead of being evaluated.
+template <typename R, int D, int M2, int ACC, int METHOD, bool PRE = false>
 __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
@@ -339,7 +380,13 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
             cell_of<R>(xs[j * D + t], L, n, theta[t]);
             r[t] = n + L / 2 - n0[t];
         }
-        if constexpr (std::is_same<R, float>::value) {
+        if constexpr (PRE) {
+            const R* __restrict__ wp = static_cast<const R*>(a.wpre) + j * (D * M2);
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+#pragma unroll
+                for (int o = 0; o < M2; ++o) w[t][o] = wp[t * M2 + o];
+        } else if constexpr (std::is_same<R, float>::value) {
             // m <= 6: coefficients straight from the kernel arguments (SGPRs); larger m
             // would spill SGPRs, so those read them from LDS (broadcast).
             if constexpr (M2 <= 12) weights_poly<D, M2, kPolyCoef>(theta, a.poly, w, a.edge_k);
@@ -433,37 +480,68 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
 
 using GatherFn = void (*)(GatherArgs);
 
-template <typename R, int D, int ACC, int METHOD>
+template <typename R, int D, int ACC, int METHOD, bool PRE>
 GatherFn pick_m(int m) {
     switch (m) {
-        case 2: return k_gather<R, D, 4, ACC, METHOD>;
-        case 3: return k_gather<R, D, 6, ACC, METHOD>;
-        case 4: return k_gather<R, D, 8, ACC, METHOD>;
-        case 5: return k_gather<R, D, 10, ACC, METHOD>;
-        case 6: return k_gather<R, D, 12, ACC, METHOD>;
-        case 7: return k_gather<R, D, 14, ACC, METHOD>;
-        case 8: return k_gather<R, D, 16, ACC, METHOD>;
+        case 2: return k_gather<R, D, 4, ACC, METHOD, PRE>;
+        case 3: return k_gather<R, D, 6, ACC, METHOD, PRE>;
+        case 4: return k_gather<R, D, 8, ACC, METHOD, PRE>;
+        case 5: return k_gather<R, D, 10, ACC, METHOD, PRE>;
+        case 6: return k_gather<R, D, 12, ACC, METHOD, PRE>;
+        case 7: return k_gather<R, D, 14, ACC, METHOD, PRE>;
+        case 8: return k_gather<R, D, 16, ACC, METHOD, PRE>;
         default: return nullptr;
     }
 }
 
-template <typename R, int ACC, int METHOD>
+template <typename R, int ACC, int METHOD, bool PRE = false>
 GatherFn pick_d(int d, int m) {
     switch (d) {
-        case 1: return pick_m<R, 1, ACC, METHOD>(m);
-        case 2: return pick_m<R, 2, ACC, METHOD>(m);
-        case 3: return pick_m<R, 3, ACC, METHOD>(m);
+        case 1: return pick_m<R, 1, ACC, METHOD, PRE>(m);
+        case 2: return pick_m<R, 2, ACC, METHOD, PRE>(m);
+        case 3: return pick_m<R, 3, ACC, METHOD, PRE>(m);
         default: return nullptr;
     }
 }
 
 GatherFn pick_gather(const Plan& p) {
     const int M = p.method == BL_NFFT ? 1 : 0;
+    if (p.use_wpre && !M) {   // precomputed weights: Algorithm 4.2 only
+        if (p.prec == BL_F64) return pick_d<double, 0, 0, true>(p.d, p.m);
+        if (p.prec == BL_F32) return pick_d<float, 0, 0, true>(p.d, p.m);
+        return pick_d<float, 1, 0, true>(p.d, p.m);
+    }
     if (p.prec == BL_F64)
         return M ? pick_d<double, 0, 1>(p.d, p.m) : pick_d<double, 0, 0>(p.d, p.m);
     if (p.prec == BL_F32)
         return M ? pick_d<float, 0, 1>(p.d, p.m) : pick_d<float, 0, 0>(p.d, p.m);
     return M ? pick_d<float, 1, 1>(p.d, p.m) : pick_d<float, 1, 0>(p.d, p.m);
+}
+
+using WeightsFn = void (*)(GatherArgs);
+
+template <typename R, int D>
+WeightsFn pick_weights_m(int m) {
+    switch (m) {
+        case 2: return k_weights<R, D, 4>;
+        case 3: return k_weights<R, D, 6>;
+        case 4: return k_weights<R, D, 8>;
+        case 5: return k_weights<R, D, 10>;
+        case 6: return k_weights<R, D, 12>;
+        case 7: return k_weights<R, D, 14>;
+        case 8: return k_weights<R, D, 16>;
+        default: return nullptr;
+    }
+}
+
+template <typename R>
+WeightsFn pick_weights(int d, int m) {
+    switch (d) {
+        case 1: return pick_weights_m<R, 1>(m);
+        case 2: return pick_weights_m<R, 2>(m);
+        case 3: return pick_weights_m<R, 3>(m);
+        default: return nullptr;
+    }
 }
 
 }  // namespace
@@ -637,10 +715,34 @@ bl_status launch_gather(Plan& p, const void* theta, void* f) {
     for (size_t i = 0; i < p.poly64.size() && i < size_t(kMaxM * kPolyCoef64); ++i) a.poly64[i] = p.poly64[i];
     a.use_poly64 = p.use_poly64 ? 1 : 0;
     a.edge_k = float(p.edge_k);
+    a.wpre = p.use_wpre ? p.d_wpre : nullptr;
     const size_t lds = gather_lds_bytes(p) + 16 + sizeof(double) * kMaxM * kPolyCoef64;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);
+    BL_HIP(hipGetLastError());
+    return BL_OK;
+}
+
+bl_status launch_weights(Plan& p) {
+    if (p.N == 0) return BL_OK;
+    WeightsFn fn = p.prec == BL_F64 ? pick_weights<double>(p.d, p.m) : pick_weights<float>(p.d, p.m);
+    if (!fn) {
+        set_error("no weight kernel for this (d, m)");
+        return BL_EUNSUPPORTED;
+    }
+    GatherArgs a{};
+    a.xs = p.d_xs;
+    a.L = int(p.L);
+    a.beta = p.beta;
+    a.cb = 1.0 / (-std::expm1(-2.0 * p.beta));
+    for (size_t i = 0; i < p.poly.size() && i < size_t(kMaxM * kPolyCoef); ++i) a.poly[i] = p.poly[i];
+    for (size_t i = 0; i < p.poly64.size() && i < size_t(kMaxM * kPolyCoef64); ++i) a.poly64[i] = p.poly64[i];
+    a.use_poly64 = p.use_poly64 ? 1 : 0;
+    a.edge_k = float(p.edge_k);
+    a.wpre = p.d_wpre;
+    a.N = p.N;
+    hipLaunchKernelGGL(fn, dim3(unsigned((p.N + 255) / 256)), dim3(256), 0, p.stream, a);
     BL_HIP(hipGetLastError());
     return BL_OK;
 }

@@ -117,6 +117,13 @@ class Plan:
         """(node binding, forward) counters: identifies the samples theta the plan holds."""
         return (self._nodes_version, self._forward_version)
 
+    def precompute_weights(self, enable: bool = True) -> None:
+        """Store the bound nodes' window weights once (Algorithm 4.2, step 0b) for later
+        transforms with the same nodes; enable=False returns to on-the-fly weights."""
+        with self._dev():
+            check(self._lib.bl_precompute_weights(self.handle, int(bool(enable))),
+                  "bl_precompute_weights")
+
     def interpolate(self, theta: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         self._check(theta, (self.L,) * self.d, self.complex_dtype, "theta")
         if out is None:

@@ -396,3 +396,44 @@ def test_ckb_fp64_grad_x_is_refused():
     with pytest.raises(BLNFFTError) as e:
         plan.grad_x(f)
     assert e.value.status == 6
+
+
+@pytest.mark.parametrize("d,M,L,m,N", [(1, 64, 128, 5, 3000), (2, 64, 128, 5, 5000),
+                                       (3, 16, 32, 4, 3000), (2, 32, 64, 8, 2000)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32c"])
+def test_precomputed_weights(d, M, L, m, N, prec):
+    """Algorithm 4.2 step 0b with stored weights: the same weight arithmetic as on the fly,
+    so forward and interpolate results are identical; rebinding discards the weights."""
+    p = W.custom_problem(d, M, L, m, N, seed=1100 + d + m, precision="f32" if prec != "f64" else "f64")
+    plan = make_plan(p, prec)
+    plan.set_nodes(dev_real(p.x, prec))
+    fh = dev_cplx(p.fhat, prec)
+    f0 = host(plan.forward(fh))
+    plan.precompute_weights(True)
+    f1 = host(plan.forward(fh))
+    assert np.array_equal(f0, f1)
+    assert O.rel_err_inf(f1, O.forward_shannon(p.fhat, p.x, L, m)) <= TOL[prec]
+    theta = plan.theta()
+    assert np.array_equal(host(plan.interpolate(theta)), f1)
+    q = W.custom_problem(d, M, L, m, N // 2, seed=1200 + d + m, precision="f32" if prec != "f64" else "f64")
+    plan.set_nodes(dev_real(q.x, prec))                 # discards the stored weights
+    g0 = host(plan.forward(fh))
+    assert O.rel_err_inf(g0, O.forward_shannon(p.fhat, q.x, L, m)) <= TOL[prec]
+    plan.precompute_weights(True)
+    assert np.array_equal(host(plan.forward(fh)), g0)
+    plan.precompute_weights(False)
+    assert np.array_equal(host(plan.forward(fh)), g0)
+
+
+def test_precomputed_weights_states():
+    from paper_2502_07155_amd._lib import BLNFFTError
+    p = W.custom_problem(2, 32, 64, 4, 100, seed=5, precision="f64")
+    plan = make_plan(p, "f64")
+    with pytest.raises(BLNFFTError) as e:
+        plan.precompute_weights(True)
+    assert e.value.status == 5
+    nf = make_plan(p, "f64", "nfft")
+    nf.set_nodes(dev_real(p.x, "f64"))
+    with pytest.raises(BLNFFTError) as e:
+        nf.precompute_weights(True)
+    assert e.value.status == 6
