@@ -68,10 +68,20 @@ def parse():
     return ap.parse_args()
 
 
-def gather_flops_per_node(d: int, m: int) -> int:
-    """Algorithmic flops of one node's short sum: (2m)^d terms, each a real weight times
-    a complex sample accumulated (2 FMA = 4 flops).  Weight evaluation is not counted."""
+WEIGHT_EVAL_FLOPS = 25   # one window weight psi(x - l/L): sinc, sqrt, sinh/exp, products
+
+
+def mac_flops_per_node(d: int, m: int) -> int:
+    """The contraction of one node's short sum: (2m)^d terms, each a real weight times a
+    complex sample accumulated (2 FMA = 4 flops)."""
     return 4 * (2 * m) ** d
+
+
+def gather_flops_per_node(d: int, m: int) -> int:
+    """Algorithmic flops of one node's short sum: the contraction plus its d x 2m weight
+    evaluations at WEIGHT_EVAL_FLOPS each (the compensated FP32C outer sum is not counted
+    as extra work)."""
+    return mac_flops_per_node(d, m) + WEIGHT_EVAL_FLOPS * d * 2 * m
 
 
 def algorithmic_bytes(d, M, L, N, csize: int, rsize: int) -> dict:
@@ -638,7 +648,9 @@ def main():
                      "achieved": gather_tflops, "peak": peak, "unit": "TFLOP/s",
                      "frac": gather_tflops / peak, "traffic": traffic,
                      "algorithmic_flops_per_launch": flops,
-                     "per_node_flops": gather_flops_per_node(p.d, p.m)},
+                     "per_node_flops": gather_flops_per_node(p.d, p.m),
+                     "per_node_flops_contraction_only": mac_flops_per_node(p.d, p.m),
+                     "frac_contraction_only": mac_flops_per_node(p.d, p.m) * p.N / (gms * 1e-3) / 1e12 / peak},
         "hbm": {"algorithmic_bytes": ab, "deconv_fft_GBs": ab["fft"] / (fft_ms * 1e-3) / 1e9,
                 "gather_GBs": ab["gather"] / (gms * 1e-3) / 1e9, "peak_GBs": HBM_PEAK_GBS},
     }
