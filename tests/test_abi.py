@@ -118,6 +118,8 @@ def test_calls_with_null_plan(lib):
     assert lib.bl_forward(None, None, None) == 1
     assert lib.bl_adjoint(None, None, None) == 1
     assert lib.bl_grad_x(None, None, None) == 1
+    assert lib.bl_interpolate(None, None, None) == 1
+    assert lib.bl_precompute_weights(None, 1) == 1
     assert lib.bl_plan_destroy(None) == 0
 
 
