@@ -96,10 +96,10 @@ struct Plan {
     std::vector<double> poly64;
     double poly64_err = 0.0;
     bool use_poly64 = false;
-    double edge_k = 1.0;
-    bool fft_ok = true;
+    double edge_k = 1.0;           // edge exponent of the weight polynomials (edge_exponent)
+    bool fft_ok = true;            // L is a power of two >= 16: steps 1-2 and the adjoint available
     void* d_wpre = nullptr;        // precomputed weights (bl_precompute_weights), binned order
-    bool use_wpre = false;            // L is a power of two >= 16: steps 1-2 (and the adjoint) available           // edge exponent of the weight polynomials (edge_exponent)
+    bool use_wpre = false;
     // Inverse-direction twiddles for the adjoint are the conjugates; computed in kernel.
 
     // FFT ping-pong buffers and the grid of theta (L^d complex).
