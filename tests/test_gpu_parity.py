@@ -437,3 +437,15 @@ def test_precomputed_weights_states():
     with pytest.raises(BLNFFTError) as e:
         nf.precompute_weights(True)
     assert e.value.status == 6
+
+
+@pytest.mark.parametrize("prec", ["f32c", "f64"])
+def test_largest_lines_d2(prec):
+    """Maximum per-plan line length, L = 8192 in d = 2 (radix-16 FFT passes, a 2^26-point grid),
+    against the oracle on every node."""
+    p = W.custom_problem(2, 4096, 8192, 4, 20000, seed=77, precision="f32" if prec != "f64" else "f64")
+    plan = make_plan(p, prec)
+    plan.set_nodes(dev_real(p.x, prec))
+    f = host(plan.forward(dev_cplx(p.fhat, prec)))
+    fo = O.forward_shannon(p.fhat, p.x, 8192, 4)
+    assert O.rel_err_inf(f, fo) <= TOL[prec]
