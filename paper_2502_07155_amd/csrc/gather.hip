@@ -268,7 +268,10 @@ __global__ void __launch_bounds__(256) k_weights(GatherArgs a) {
 }
 
 // PRE: the weights come from a.wpre (bl_precompute_weights) instead of being evaluated.
-template <typename R, int D, int M2, int ACC, int METHOD, bool PRE = false>
+// EXACT (double only): the closed-form weights instead of the double polynomials; a
+// separate instantiation, so that the polynomial kernel's registers are not sized for
+// the closed form.
+template <typename R, int D, int M2, int ACC, int METHOD, bool PRE = false, bool EXACT = false>
 __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
@@ -306,9 +309,8 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
         for (int e = threadIdx.x; e < m * kPolyCoef; e += blockDim.x) coef[e] = a.poly[e];
     }
     double* coef64 = reinterpret_cast<double*>(coef);
-    if constexpr (std::is_same<R, double>::value) {
-        if (a.use_poly64)
-            for (int e = threadIdx.x; e < m * kPolyCoef64; e += blockDim.x) coef64[e] = a.poly64[e];
+    if constexpr (std::is_same<R, double>::value && !EXACT && !PRE) {
+        for (int e = threadIdx.x; e < m * kPolyCoef64; e += blockDim.x) coef64[e] = a.poly64[e];
     }
     // Stage the tile plus halo.  Element e of the box is split into per-dimension
     // coordinates by multiplying with wdiv[t] = floor(2^20 / W[t]) + 1 (exact division
@@ -391,7 +393,7 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
             // would spill SGPRs, so those read them from LDS (broadcast).
             if constexpr (M2 <= 12) weights_poly<D, M2, kPolyCoef>(theta, a.poly, w, a.edge_k);
             else weights_poly<D, M2, kPolyCoef>(theta, coef, w, a.edge_k);
-        } else if (a.use_poly64) {
+        } else if constexpr (!EXACT) {
             // An opaque zero offset keeps the (uniform, LDS) coefficient loads inside the
             // node loop instead of holding every coefficient in registers.
             int opaque = 0;
@@ -480,26 +482,26 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
 
 using GatherFn = void (*)(GatherArgs);
 
-template <typename R, int D, int ACC, int METHOD, bool PRE>
+template <typename R, int D, int ACC, int METHOD, bool PRE, bool EXACT>
 GatherFn pick_m(int m) {
     switch (m) {
-        case 2: return k_gather<R, D, 4, ACC, METHOD, PRE>;
-        case 3: return k_gather<R, D, 6, ACC, METHOD, PRE>;
-        case 4: return k_gather<R, D, 8, ACC, METHOD, PRE>;
-        case 5: return k_gather<R, D, 10, ACC, METHOD, PRE>;
-        case 6: return k_gather<R, D, 12, ACC, METHOD, PRE>;
-        case 7: return k_gather<R, D, 14, ACC, METHOD, PRE>;
-        case 8: return k_gather<R, D, 16, ACC, METHOD, PRE>;
+        case 2: return k_gather<R, D, 4, ACC, METHOD, PRE, EXACT>;
+        case 3: return k_gather<R, D, 6, ACC, METHOD, PRE, EXACT>;
+        case 4: return k_gather<R, D, 8, ACC, METHOD, PRE, EXACT>;
+        case 5: return k_gather<R, D, 10, ACC, METHOD, PRE, EXACT>;
+        case 6: return k_gather<R, D, 12, ACC, METHOD, PRE, EXACT>;
+        case 7: return k_gather<R, D, 14, ACC, METHOD, PRE, EXACT>;
+        case 8: return k_gather<R, D, 16, ACC, METHOD, PRE, EXACT>;
         default: return nullptr;
     }
 }
 
-template <typename R, int ACC, int METHOD, bool PRE = false>
+template <typename R, int ACC, int METHOD, bool PRE = false, bool EXACT = false>
 GatherFn pick_d(int d, int m) {
     switch (d) {
-        case 1: return pick_m<R, 1, ACC, METHOD, PRE>(m);
-        case 2: return pick_m<R, 2, ACC, METHOD, PRE>(m);
-        case 3: return pick_m<R, 3, ACC, METHOD, PRE>(m);
+        case 1: return pick_m<R, 1, ACC, METHOD, PRE, EXACT>(m);
+        case 2: return pick_m<R, 2, ACC, METHOD, PRE, EXACT>(m);
+        case 3: return pick_m<R, 3, ACC, METHOD, PRE, EXACT>(m);
         default: return nullptr;
     }
 }
@@ -511,8 +513,10 @@ GatherFn pick_gather(const Plan& p) {
         if (p.prec == BL_F32) return pick_d<float, 0, 0, true>(p.d, p.m);
         return pick_d<float, 1, 0, true>(p.d, p.m);
     }
-    if (p.prec == BL_F64)
-        return M ? pick_d<double, 0, 1>(p.d, p.m) : pick_d<double, 0, 0>(p.d, p.m);
+    if (p.prec == BL_F64) {
+        if (p.use_poly64) return M ? pick_d<double, 0, 1>(p.d, p.m) : pick_d<double, 0, 0>(p.d, p.m);
+        return M ? pick_d<double, 0, 1, false, true>(p.d, p.m) : pick_d<double, 0, 0, false, true>(p.d, p.m);
+    }
     if (p.prec == BL_F32)
         return M ? pick_d<float, 0, 1>(p.d, p.m) : pick_d<float, 0, 0>(p.d, p.m);
     return M ? pick_d<float, 1, 1>(p.d, p.m) : pick_d<float, 1, 0>(p.d, p.m);

@@ -449,3 +449,20 @@ def test_largest_lines_d2(prec):
     f = host(plan.forward(dev_cplx(p.fhat, prec)))
     fo = O.forward_shannon(p.fhat, p.x, 8192, 4)
     assert O.rel_err_inf(f, fo) <= TOL[prec]
+
+
+@pytest.mark.parametrize("d,M,L,m,N", [(1, 64, 128, 5, 2000), (2, 64, 128, 5, 4000), (3, 16, 32, 4, 2000)])
+@pytest.mark.parametrize("method", ["shannon", "nfft"])
+def test_fp64_exact_weights(d, M, L, m, N, method, monkeypatch):
+    """FP64 with the closed-form weights (the kernels used when a double polynomial fit
+    would miss 1e-13): forward, interpolate and adjoint against the oracle."""
+    monkeypatch.setenv("BL_EXACT_WEIGHTS", "1")
+    p = W.custom_problem(d, M, L, m, N, seed=1300 + d + m, precision="f64", with_targets=True)
+    plan = make_plan(p, "f64", method)
+    plan.set_nodes(dev_real(p.x, "f64"))
+    f = host(plan.forward(dev_cplx(p.fhat, "f64")))
+    fo = (O.forward_shannon if method == "shannon" else O.forward_nfft)(p.fhat, p.x, L, m)
+    assert O.rel_err_inf(f, fo) <= 1e-12
+    a = host(plan.adjoint(dev_cplx(p.y, "f64")))
+    ao = (O.adjoint_shannon if method == "shannon" else O.adjoint_nfft)(p.y, p.x, M, L, m)
+    assert O.rel_err_inf(a, ao) <= 1e-12
