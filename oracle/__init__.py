@@ -6,7 +6,7 @@ with the GPU library.
 """
 from .blnfft_oracle import *  # noqa: F401,F403
 from .blnfft_oracle import (  # noqa: F401
-    adjoint_nfft, adjoint_shannon, band, default_beta, dense_forward, dense_Psi,
+    adjoint_at, adjoint_nfft, adjoint_shannon, band, default_beta, dense_forward, dense_Psi,
     dense_B, dense_F, dense_D, deconvolve_pad, direct_sum, dirichlet, example51_f,
     exp_approx_nfft, exp_approx_shannon, exp_samples, fig51_frequencies,
     forward_nfft, forward_shannon, gather_nfft, gather_shannon, grad_x_shannon,

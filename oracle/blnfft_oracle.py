@@ -512,6 +512,49 @@ def adjoint_nfft(g: np.ndarray, x: np.ndarray, M: int, L: int, m: int,
     return Ak / (L ** d * _outer_product([h1] * d))
 
 
+def adjoint_at(g: np.ndarray, x: np.ndarray, M: int, L: int, m: int, ks,
+               method: str = "shannon", beta: float | None = None,
+               win: str = "sinh") -> np.ndarray:
+    """Entries (A^H g)(k) of the adjoint for the frequencies k in ks (K x d integers in
+    [-M/2, M/2)), one at a time from the matrix factorisation ((4.11); for the classical
+    NFFT, (2.4)-(2.6)):
+
+        (A^H g)(k) = sum_j g_j prod_t [sum_{l_t} w(L x_jt - l_t) e^{-2 pi i k_t l_t / L}]
+                     / (L^d prod_t what(k_t)),
+
+    with w = psi and l_t over I_L only (Psi has no columns outside I_L), or w = phi with
+    l_t wrapped mod L (the phase is unchanged by the wrap), and what the window's
+    transform.  The inner sum runs over the candidates of node_offsets.  For checking
+    sampled entries of adjoints too large for the dense or FFT forms."""
+    d = x.shape[1]
+    ks = np.atleast_2d(np.asarray(ks, dtype=np.int64))
+    if beta is None:
+        beta = default_beta(M, L, m, method)
+    hat = psihat1 if method == "shannon" else phihat1
+    cols = []
+    for t in range(d):
+        ell, off, edge = node_offsets(x[:, t], L, m)
+        if method == "shannon":
+            w = psi_g(off, m, beta, win, edge) * ((ell >= -(L // 2)) & (ell < L // 2))
+        else:
+            w = phi_g(off, m, beta, win, edge)
+        cols.append((ell, w))
+    lmin = -(L // 2) - m                                # smallest candidate l
+    lall = np.arange(lmin, L // 2 + m + 1, dtype=np.int64)
+    out = np.empty(len(ks), dtype=np.complex128)
+    for i, k in enumerate(ks):
+        prod = np.asarray(g, dtype=np.complex128).copy()
+        scale = float(L) ** d
+        for t in range(d):
+            ell, w = cols[t]
+            r = np.mod(int(k[t]) * lall, L)             # k l mod L, exact
+            phase = cospi(2.0 * r / L) - 1j * sinpi(2.0 * r / L)   # e^{-2 pi i k l / L}
+            prod = prod * (w * phase[ell - lmin]).sum(axis=1)
+            scale *= float(hat(np.array([float(k[t])]), L, m, beta, win)[0])
+        out[i] = prod.sum() / scale
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Targets: the direct trigonometric sum (2.1) and closed forms
 # ---------------------------------------------------------------------------

@@ -399,6 +399,34 @@ def test_adjoint_equals_dense_conjugate_transpose():
     assert O.rel_err_inf(O.adjoint_shannon(p.y, p.x, M, L, m), ref) < 1e-13
 
 
+def test_adjoint_entries_equal_dense_conjugate_transpose():
+    """adjoint_at (entries of A^H g one frequency at a time) against the dense A^H of (4.11)
+    and the dense B^H of (2.4)-(2.6), including nodes whose windows leave I_L."""
+    d, M, L, m, N = 2, 6, 12, 2, 20
+    p = W.custom_problem(d, M, L, m, N, seed=71, with_targets=True)
+    ks = np.array([[-3, -3], [0, 0], [2, -1], [-1, 2], [2, 2]])
+    idx = tuple((ks + M // 2).T)
+    beta = O.default_beta(M, L, m)
+    A = O.dense_Psi(p.x, L, m, beta) @ O.dense_F(M, L, d) @ np.diag(O.dense_D(M, L, d, m, beta))
+    ref = (A.conj().T @ p.y).reshape(M, M)[idx]
+    assert O.rel_err_inf(O.adjoint_at(p.y, p.x, M, L, m, ks), ref) < 1e-13
+    bn = O.default_beta(M, L, m, "nfft")
+    B = O.dense_B(p.x, L, m, bn) @ O.dense_F(M, L, d) @ np.diag(O.dense_D(M, L, d, m, bn, method="nfft"))
+    refn = (B.conj().T @ p.y).reshape(M, M)[idx]
+    assert O.rel_err_inf(O.adjoint_at(p.y, p.x, M, L, m, ks, method="nfft"), refn) < 1e-13
+
+
+@pytest.mark.parametrize("d,M,L,m,N", [(1, 16, 40, 4, 60), (3, 8, 16, 3, 50)])
+def test_adjoint_entries_equal_fft_adjoints(d, M, L, m, N):
+    p = W.custom_problem(d, M, L, m, N, seed=72 + d, with_targets=True)
+    ks = W.rng_for(73).integers(-M // 2, M // 2, size=(6, d))
+    idx = tuple((ks + M // 2).T)
+    full = O.adjoint_shannon(p.y, p.x, M, L, m)
+    assert O.rel_err_inf(O.adjoint_at(p.y, p.x, M, L, m, ks), full[idx]) < 1e-13
+    fulln = O.adjoint_nfft(p.y, p.x, M, L, m)
+    assert O.rel_err_inf(O.adjoint_at(p.y, p.x, M, L, m, ks, method="nfft"), fulln[idx]) < 1e-13
+
+
 def test_grad_x_matches_richardson_finite_differences():
     M, L, m = 16, 32, 4
     p = W.custom_problem(2, M, L, m, 20, seed=5, with_targets=True)
