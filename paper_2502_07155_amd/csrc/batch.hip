@@ -528,16 +528,6 @@ struct BGatherArgs {
     int tile;
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs; map them so that consecutive
-// work-list entries (the same instance: its samples and its outputs) share one XCD's L2.
-__device__ __forceinline__ int xcd_block(int p, int n) {
-    constexpr int X = 8;
-    const int x = p % X;
-    const int q = n / X, r = n % X;
-    const int start = x * q + (x < r ? x : r);
-    return start + p / X;
-}
-
 template <int M2, int ACC>
 __device__ __forceinline__ void batch_gather_chunk(const BGatherArgs& a, const int4 ch, const InstDesc& d,
                                                    unsigned char* smem_raw) {

@@ -42,6 +42,19 @@ constexpr bool dual_tiles_for(int d, int m, bool is_float) {
     return is_float && (d == 2 || (d == 3 && m <= 5));
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Maps the
+// hardware block index p (of n) to a logical one so that each XCD runs one contiguous
+// range of logical blocks: neighbouring work items (strided FFT lines, adjacent tiles
+// with overlapping halos, entries of one batched instance) then share an L2.  A
+// bijection of [0, n).
+__device__ __forceinline__ int xcd_block(int p, int n) {
+    constexpr int X = 8;
+    const int x = p % X;
+    const int q = n / X, r = n % X;
+    const int start = x * q + (x < r ? x : r);
+    return start + p / X;
+}
+
 // Factorisation of one FFT length into Stockham stages.
 struct FftFactors {
     int L = 0;

@@ -214,17 +214,6 @@ __device__ __forceinline__ void last_stage(Cx<R>* reg, Cx<R>* lds, const Cx<R>* 
     stage_write<R, E, DIR, RAD, CONTIG, 1>(reg, lds, tw, io, lgL, lgB, Lp, Ns, tid, NT);
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Map the
-// hardware block index to a logical one so that consecutive logical blocks (neighbouring
-// lines, which share cache lines in strided passes) run on the same XCD.
-__device__ __forceinline__ int xcd_block(int p, int n) {
-    constexpr int X = 8;
-    const int x = p % X;
-    const int q = n / X, r = n % X;
-    const int start = x * q + (x < r ? x : r);
-    return start + p / X;
-}
-
 // Threads per workgroup: 1024 with four values per thread, 512 with sixteen (register
 // pressure of the radix-16 butterflies in double).
 template <int E>

@@ -276,7 +276,9 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
     constexpr int m = M2 / 2;
-    const int4 ch = a.chunks[blockIdx.x];
+    // Chunks are in tile order, so an XCD's consecutive chunks are neighbouring tiles whose
+    // halos overlap in its L2 (measured: 1-2 us less for d = 2, FP32C; 4 us for FP64).
+    const int4 ch = a.chunks[xcd_block(int(blockIdx.x), int(gridDim.x))];
     const int L = a.L;
     // tile origin (cell index in [0, L)) and LDS extents
     int n0[3] = {0, 0, 0}, W[3] = {1, 1, 1};

@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R* acc = reinterpret_cast<R*>(smem_raw);   // interleaved re, im
     constexpr int m = M2 / 2;
-    const int4 ch = a.chunks[blockIdx.x];
+    const int4 ch = a.chunks[xcd_block(int(blockIdx.x), int(gridDim.x))];
     const int L = a.L;
     int n0[3] = {0, 0, 0}, W[3] = {1, 1, 1};
     tile_geometry<D>(ch, a.tpd, a.tile, M2, n0, W);
@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(kOsThreads) k_spread_os(SpreadArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int m = M2 / 2;
     constexpr int KP = os_points<D>();
-    const int4 ch = a.chunks[blockIdx.x];
+    const int4 ch = a.chunks[xcd_block(int(blockIdx.x), int(gridDim.x))];
     const int L = a.L;
     const int tid = threadIdx.x;
     int n0[3] = {0, 0, 0}, W[3] = {1, 1, 1}, T[3] = {1, 1, 1};
@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
     int* key = rowstart + 48;                             // [NB]
     float* coef = reinterpret_cast<float*>(key + NB);
 
-    const int4 ch = a.chunks[blockIdx.x];
+    const int4 ch = a.chunks[xcd_block(int(blockIdx.x), int(gridDim.x))];
     const int L = a.L;
     const int tid = threadIdx.x;
     int n0[3] = {0, 0, 0}, W[3] = {1, 1, 1};
@@ -500,12 +500,180 @@ __global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
     }
 }
 
+// d = 3 spreading by box columns.  Thread t owns the box column (c1, c2) = (t div 16,
+// t mod 16) with every c0 in registers, so boxes of at most 16^3 points are covered by 256
+// threads; wave w holds c1 in [4w, 4w + 4).  For a batch of the chunk's nodes, LDS holds
+// the second and last dimensions' weights at absolute box coordinates (zero elsewhere) and
+// the first dimension's weights by offset.  The batch is sorted by cell, so for each tile
+// row r0 the nodes whose windows reach the wave's c1 range are one contiguous range; they
+// add to c0 in [r0, r0 + 2m), fixed accumulator registers because r0 is a compile-time
+// constant in each unrolled pass.  Nodes at the ends of a 16-byte group outside that range are masked.
+// f(std::integral_constant<int, I>) for I = 0 .. N-1, each with I a constant expression.
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
+
+constexpr int kRows3Box = 16;                                // box extent bound per dimension
+constexpr int kRows3Starts = kRows3Box * (kRows3Box + 1);    // [r0][r1] start table
+template <typename R>
+constexpr size_t rows3_lds_bytes(int M2) {
+    return sizeof(R) * size_t(M2 + 2 * kRows3Box) * rows_pitch<R>() + sizeof(Cx<R>) * rows_batch<R>() +
+           sizeof(int) * (rows_batch<R>() + kRows3Starts) + sizeof(float) * kMaxM * kPolyCoef;
+}
+
+template <typename R, int M2, int METHOD>
+__global__ void __launch_bounds__(256) k_spread_rows3(SpreadArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int m = M2 / 2;
+    constexpr int NB = rows_batch<R>();
+    constexpr int P = rows_pitch<R>();
+    constexpr int VEC = 16 / int(sizeof(R));   // nodes per 16-byte load
+    constexpr int C = kRows3Box;
+    constexpr int R0 = C - M2 + 1;              // tile rows along the first dimension
+    typedef R vec_t __attribute__((ext_vector_type(VEC)));
+    R* w0s = reinterpret_cast<R*>(smem_raw);   // [M2][P]: first-dimension weight by offset
+    R* w1s = w0s + M2 * P;                     // [C][P]: second-dimension weight at box c1
+    R* w2s = w1s + C * P;                      // [C][P]: last-dimension weight at box c2
+    Cx<R>* gv = reinterpret_cast<Cx<R>*>(w2s + C * P);   // [NB]
+    int* key = reinterpret_cast<int*>(gv + NB);          // [NB]
+    int* cstart = key + NB;                              // [r0 (C + 1) + r1]
+    float* coef = reinterpret_cast<float*>(cstart + kRows3Starts);
+
+    const int4 ch = a.chunks[xcd_block(int(blockIdx.x), int(gridDim.x))];
+    const int L = a.L;
+    const int tid = threadIdx.x;
+    int n0[3] = {0, 0, 0}, W[3] = {1, 1, 1};
+    tile_geometry<3>(ch, a.tpd, a.tile, M2, n0, W);
+    const int T0 = a.tile[0], T1 = a.tile[1], T2 = a.tile[2];
+    if constexpr (std::is_same<R, float>::value) {
+        for (int e = tid; e < m * kPolyCoef; e += blockDim.x) coef[e] = a.poly[e];
+    }
+    const int wv = tid >> 6;
+    const int c1 = tid >> 4, c2 = tid & (C - 1);
+    // tile rows along the second dimension whose nodes reach box rows [4 wv, 4 wv + 4)
+    const int r1lo = max(0, 4 * wv - M2 + 1), r1hi = min(T1 - 1, 4 * wv + 3);
+    Cx<R> acc[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc[k] = Cx<R>{R(0), R(0)};
+
+    const R* __restrict__ xs = static_cast<const R*>(a.xs);
+    const Cx<R>* __restrict__ g = static_cast<const Cx<R>*>(a.g);
+    const R beta = R(a.beta), cbeta = R(a.cb), inv_m2 = R(1) / R(m * m);
+    for (int b0 = 0; b0 < ch.z; b0 += NB) {
+        const int nb = min(NB, ch.z - b0);
+        __syncthreads();   // coefficients staged / previous batch consumed
+        {
+            vec_t* z = reinterpret_cast<vec_t*>(w1s);
+            for (int e = tid; e < 2 * C * P / VEC; e += blockDim.x) z[e] = vec_t(R(0));
+        }
+        __syncthreads();
+        if (tid < nb) {
+            const int64_t j = int64_t(ch.y) + b0 + tid;
+            R theta[3];
+            int r[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                int nc;
+                cell_of<R>(xs[j * 3 + t], L, nc, theta[t]);
+                r[t] = nc + L / 2 - n0[t];
+            }
+            R w[3][M2];
+            if constexpr (std::is_same<R, float>::value) {
+                weights_poly<3, M2, kPolyCoef>(theta, coef, w, a.edge_k);
+            } else if (a.use_poly64) {
+                weights_poly64<3, M2, kPolyCoef64>(theta, a.poly64, w, double(a.edge_k));
+            } else {
+#pragma unroll
+                for (int t = 0; t < 3; ++t) weights<R, M2, METHOD>(theta[t], beta, cbeta, inv_m2, w[t]);
+            }
+#pragma unroll
+            for (int o = 0; o < M2; ++o) {
+                w0s[o * P + tid] = w[0][o];
+                w1s[(r[1] + o) * P + tid] = w[1][o];
+                w2s[(r[2] + o) * P + tid] = w[2][o];
+            }
+            gv[tid] = g[a.perm[j]];
+            key[tid] = (r[0] * T1 + r[1]) * T2 + r[2];
+        } else if (tid < NB) {
+            // past the batch (read at group ends, masked): finite zeros
+#pragma unroll
+            for (int o = 0; o < M2; ++o) w0s[o * P + tid] = R(0);
+            gv[tid] = Cx<R>{R(0), R(0)};
+        }
+        __syncthreads();
+        // cstart[r0 (C + 1) + r1] = first batch position in cell row (r0, r1) or later
+        for (int e = tid; e < T0 * (T1 + 1); e += blockDim.x) {
+            const int r0 = e / (T1 + 1), r1 = e - r0 * (T1 + 1);
+            const int c = (r0 * T1 + r1) * T2;
+            int lo = 0, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key[mid] < c) lo = mid + 1;
+                else hi = mid;
+            }
+            cstart[r0 * (C + 1) + r1] = lo;
+        }
+        __syncthreads();
+        if (r1lo > r1hi) continue;
+        const R* w1p = w1s + c1 * P;
+        const R* w2p = w2s + c2 * P;
+        static_for<R0>([&](auto r0c) __attribute__((always_inline)) {
+            constexpr int r0 = decltype(r0c)::value;
+            if (r0 >= T0) return;
+            const int jb = cstart[r0 * (C + 1) + r1lo], je = cstart[r0 * (C + 1) + r1hi + 1];
+            for (int j = jb & ~(VEC - 1); j < je; j += VEC) {
+                const vec_t v1 = *reinterpret_cast<const vec_t*>(w1p + j);
+                const vec_t v2 = *reinterpret_cast<const vec_t*>(w2p + j);
+                vec_t v0[M2];
+#pragma unroll
+                for (int o = 0; o < M2; ++o) v0[o] = *reinterpret_cast<const vec_t*>(w0s + o * P + j);
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) {
+                    const Cx<R> gq = gv[j + q];
+                    const bool in = j + q >= jb && j + q < je;
+                    const R s = in ? v1[q] * v2[q] : R(0);
+                    const R are = s * gq.re, aim = s * gq.im;
+#pragma unroll
+                    for (int o = 0; o < M2; ++o) {
+                        acc[r0 + o].re = dev_fma(v0[o][q], are, acc[r0 + o].re);
+                        acc[r0 + o].im = dev_fma(v0[o][q], aim, acc[r0 + o].im);
+                    }
+                }
+            }
+        });
+    }
+
+    if (c1 >= W[1] || c2 >= W[2]) return;
+    R* __restrict__ grid = static_cast<R*>(a.grid);
+    int p1 = n0[1] - m + 1 + c1, p2 = n0[2] - m + 1 + c2;
+    if (METHOD == 1) {
+        p1 = (p1 % L + L) % L;
+        p2 = (p2 % L + L) % L;
+    } else if (p1 < 0 || p1 >= L || p2 < 0 || p2 >= L) {
+        return;
+    }
+    static_for<C>([&](auto c0c) __attribute__((always_inline)) {
+        constexpr int c0 = decltype(c0c)::value;
+        if (c0 >= W[0] || (acc[c0].re == R(0) && acc[c0].im == R(0))) return;
+        int p0 = n0[0] - m + 1 + c0;
+        if (METHOD == 1) p0 = (p0 % L + L) % L;
+        else if (p0 < 0 || p0 >= L) return;
+        const int64_t gidx = (int64_t(p0) * L + p1) * L + p2;
+        hbm_add(grid + 2 * gidx, acc[c0].re);
+        hbm_add(grid + 2 * gidx + 1, acc[c0].im);
+    });
+}
+
 template <typename R, int D, int M2>
 __global__ void __launch_bounds__(256) k_grad_x(SpreadArgs a) {
     extern __shared__ unsigned char smem_raw[];
     Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
     constexpr int m = M2 / 2;
-    const int4 ch = a.chunks[blockIdx.x];
+    const int4 ch = a.chunks[xcd_block(int(blockIdx.x), int(gridDim.x))];
     const int L = a.L;
     int n0[3] = {0, 0, 0}, W[3] = {1, 1, 1};
     tile_geometry<D>(ch, a.tpd, a.tile, M2, n0, W);
@@ -684,6 +852,19 @@ KFn spread_rows_m(int m) {
 }
 
 template <typename R, int METHOD>
+KFn spread_rows3_m(int m) {
+    switch (m) {
+        case 2: return k_spread_rows3<R, 4, METHOD>;
+        case 3: return k_spread_rows3<R, 6, METHOD>;
+        case 4: return k_spread_rows3<R, 8, METHOD>;
+        case 5: return k_spread_rows3<R, 10, METHOD>;
+        case 6: return k_spread_rows3<R, 12, METHOD>;
+        case 7: return k_spread_rows3<R, 14, METHOD>;
+        default: return nullptr;
+    }
+}
+
+template <typename R, int METHOD>
 KFn spread_os_d(int d, int m) {
     if (d == 1) return spread_os_m<R, 1, METHOD>(m);
     if (d == 2) return spread_os_m<R, 2, METHOD>(m);
@@ -741,8 +922,9 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
     SpreadArgs a = make_args(p);
     a.g = g;
     a.grid = grid;
-    // Output-stationary kernel when the box fits its points per thread and its LDS fits;
-    // otherwise the LDS-atomic kernel.
+    // Row kernels (d = 2: box edges <= 32; d = 3: <= 16); otherwise the output-stationary
+    // kernel when the box fits its points per thread and its LDS fits; otherwise the
+    // LDS-atomic kernel.  BL_SPREAD_OS / BL_SPREAD_ATOMIC force the latter two.
     int64_t box = 1, ncell = 1;
     for (int t = 0; t < p.d; ++t) {
         box *= p.tile[t] + 2 * p.m - 1;
@@ -752,14 +934,19 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
     const size_t rs = p.prec == BL_F64 ? 8 : 4;
     const size_t os_lds = ((rs * p.d * 2 * p.m * kOsBatch + 2 * rs * kOsBatch + 4 * kOsBatch +
                             4 * size_t(ncell + 1) + 15) & ~size_t(15)) + sizeof(float) * kMaxM * kPolyCoef;
-    const bool use_rows = p.d == 2 && p.tile[0] + 2 * p.m - 1 <= 32 && p.tile[1] + 2 * p.m - 1 <= 32 &&
-                          std::getenv("BL_SPREAD_ATOMIC") == nullptr && std::getenv("BL_SPREAD_OS") == nullptr;
-    const bool use_os = !use_rows && box <= int64_t(kp) * kOsThreads && os_lds <= 64 * 1024 &&
+    const bool by_rows = std::getenv("BL_SPREAD_ATOMIC") == nullptr && std::getenv("BL_SPREAD_OS") == nullptr;
+    const bool use_rows = by_rows && p.d == 2 && p.tile[0] + 2 * p.m - 1 <= 32 && p.tile[1] + 2 * p.m - 1 <= 32;
+    bool use_rows3 = by_rows && p.d == 3 && p.m <= 7;
+    for (int t = 0; t < 3 && use_rows3; ++t) use_rows3 = p.tile[t] + 2 * p.m - 1 <= kRows3Box;
+    const bool use_os = !use_rows && !use_rows3 && box <= int64_t(kp) * kOsThreads && os_lds <= 64 * 1024 &&
                         std::getenv("BL_SPREAD_ATOMIC") == nullptr;
     KFn fn;
     if (use_rows) {
         if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_rows_m<double, 1>(p.m) : spread_rows_m<double, 0>(p.m);
         else fn = p.method == BL_NFFT ? spread_rows_m<float, 1>(p.m) : spread_rows_m<float, 0>(p.m);
+    } else if (use_rows3) {
+        if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_rows3_m<double, 1>(p.m) : spread_rows3_m<double, 0>(p.m);
+        else fn = p.method == BL_NFFT ? spread_rows3_m<float, 1>(p.m) : spread_rows3_m<float, 0>(p.m);
     } else if (use_os) {
         if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_os_d<double, 1>(p.d, p.m) : spread_os_d<double, 0>(p.d, p.m);
         else fn = p.method == BL_NFFT ? spread_os_d<float, 1>(p.d, p.m) : spread_os_d<float, 0>(p.d, p.m);
@@ -772,6 +959,7 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
         return BL_EUNSUPPORTED;
     }
     const size_t lds = use_rows ? (p.prec == BL_F64 ? rows_lds_bytes<double>() : rows_lds_bytes<float>())
+                       : use_rows3 ? (p.prec == BL_F64 ? rows3_lds_bytes<double>(2 * p.m) : rows3_lds_bytes<float>(2 * p.m))
                        : use_os ? os_lds : box_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));

@@ -243,13 +243,16 @@ def test_adjoint_matches_oracle(d, M, L, m, N, prec, method):
 
 @pytest.mark.parametrize("d,M,L,m,N,tile", [(1, 64, 128, 5, 1500, None), (2, 32, 64, 6, 40000, None),
                                             (2, 64, 128, 8, 5000, None), (2, 64, 128, 4, 5000, 24),
-                                            (3, 16, 32, 3, 1500, None)])
+                                            (3, 16, 32, 3, 1500, None), (3, 16, 32, 3, 40000, None),
+                                            (3, 32, 64, 4, 12000, None), (3, 32, 64, 2, 12000, 11)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("kernel", ["default", "BL_SPREAD_OS", "BL_SPREAD_ATOMIC"])
 def test_adjoint_spread_kernels(d, M, L, m, N, tile, prec, kernel, monkeypatch):
-    """Each spreading kernel (d = 2 row kernel, output-stationary kernel, LDS-atomic kernel)
-    against the oracle, with several node batches per chunk (N = 40000 puts about 2500
-    nodes in each of 16 tiles) and boxes that do not fit the d = 2 row kernel (tile 24)."""
+    """Each spreading kernel (d = 2 and d = 3 row kernels, output-stationary kernel,
+    LDS-atomic kernel) against the oracle, with several node batches per chunk (N = 40000
+    puts about 2500 nodes in each of 16 tiles in d = 2, 625 in each of 64 in d = 3, so
+    also several chunks per tile), boxes that do not fit the d = 2 row kernel (tile 24),
+    and d = 3 boxes of 14^3 (m = 4, tile 7; m = 2, tile 11)."""
     if kernel != "default":
         monkeypatch.setenv(kernel, "1")
     if tile is not None:
@@ -295,6 +298,27 @@ def test_full_size_adjoint_differentiation_workload():
     tho = O.inverse_fft_step(O.deconvolve_pad(p.fhat, p.L, p.m, beta))
     go = O.grad_x_from_theta(tho, host(G)[idx], p.x[idx], p.L, p.m, beta, "sinh")
     assert O.rel_err_inf(gx[idx], go) <= 2e-5
+
+
+@pytest.mark.parametrize("prec", ["f32c", "f64"])
+def test_full_size_adjoint_d3_clustered(prec):
+    """d=3, M=128, L=256, m=4, N=2e6 Gaussian-mixture nodes (dense clusters, many empty
+    tiles): the adjoint on sampled frequencies, including the band corners, against the
+    oracle's entry-by-entry adjoint."""
+    p = W.make_problem("d3_M128_L256_m4_N2M", precision="f64" if prec == "f64" else "f32")
+    rng = W.rng_for(31)
+    g = rng.standard_normal(p.N) + 1j * rng.standard_normal(p.N)
+    if prec != "f64":
+        g = g.astype(np.complex64).astype(np.complex128)
+    plan = make_plan(p, prec)
+    plan.set_nodes(dev_real(p.x, prec))
+    a = host(plan.adjoint(dev_cplx(g, prec)))
+    h = p.M // 2
+    ks = np.concatenate([np.array([[-h, -h, -h], [h - 1, h - 1, h - 1], [0, 0, 0], [-h, 0, h - 1]]),
+                         rng.integers(-h, h, size=(4, 3))])
+    ref = O.adjoint_at(g, p.x, p.M, p.L, p.m, ks)
+    got = a[tuple((ks + h).T)]
+    assert O.rel_err_inf(got, ref) <= (1e-12 if prec == "f64" else 1e-5)
 
 
 def test_graph_replays_match_eager_launches():
