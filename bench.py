@@ -51,10 +51,10 @@ def parse():
                     help="skip the oracle leg (CPU baseline and the error checks against the oracle)")
     ap.add_argument("--cpu-nodes", type=int, default=1_000_000,
                     help="nodes of the oracle's step-3 sample for the CPU baseline")
-    ap.add_argument("--leg", choices=["batched", "fwd_bwd", "nfft", "example51", "fig51"],
+    ap.add_argument("--leg", choices=["batched", "fwd_bwd", "nfft", "example51", "fig51", "adjoint"],
                     help="run only this leg (batched d=1 instances, d=2 forward + backward, "
-                         "Algorithm 2.1 on the headline workload, the Example 5.1 sweep or the "
-                         "Figure 5.1 sweep) "
+                         "Algorithm 2.1 on the headline workload, the Example 5.1 sweep, the "
+                         "Figure 5.1 sweep, or the adjoint on --workload at --precision) "
                          "and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (for counter scaling)")
@@ -510,6 +510,45 @@ def leg_differentiation(steps, warmup):
             "step": "forward + backward (grad fhat, grad x)"}
 
 
+def leg_adjoint(name, prec, steps, warmup, checks: list, nk=4):
+    """The adjoint A^H g (spreading, forward DFT passes, truncation and deconvolution) on a
+    named workload with seeded random g; the deferred check compares nk sampled
+    frequencies, including the band's two corners, with the oracle's entry-by-entry
+    adjoint."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2502_07155_amd import Plan
+    p = W.make_problem(name, precision="f64" if prec == "f64" else "f32")
+    cdt = torch.complex128 if prec == "f64" else torch.complex64
+    rdt = torch.float64 if prec == "f64" else torch.float32
+    rng = W.rng_for(91)
+    g = rng.standard_normal(p.N) + 1j * rng.standard_normal(p.N)
+    if prec != "f64":
+        g = g.astype(np.complex64).astype(np.complex128)
+    plan = Plan(p.d, p.M, p.L, p.m, precision=prec)
+    plan.set_nodes(torch.from_numpy(p.x).to(rdt).cuda())
+    gd = torch.from_numpy(g).to(cdt).cuda()
+    out = plan.adjoint(gd)
+    ms = time_calls(torch, lambda: plan.adjoint(gd, out), steps, warmup, plan.stream)
+    a = out.cpu().numpy().astype(np.complex128)
+    stats = plan.stats()
+    plan.close()
+    h = p.M // 2
+    ks = np.concatenate([np.array([[-h] * p.d, [h - 1] * p.d]), rng.integers(-h, h, size=(nk - 2, p.d))])
+    rec = {"value": p.N / (ms * 1e-3), "unit": "nodes/s", "ms_per_step": ms, "precision": prec,
+           "chunks": stats["n_chunks"], "tile": stats["tile"],
+           "step": "adjoint: spreading + forward DFT passes + truncation and deconvolution"}
+
+    def check(O):
+        ref = O.adjoint_at(g, p.x, p.M, p.L, p.m, ks)
+        rec["rel_err_inf_vs_oracle_sampled_k"] = O.rel_err_inf(a[tuple((ks + h).T)], ref)
+        rec["sampled_k"] = int(len(ks))
+    checks.append(check)
+    return rec
+
+
 def oracle_checks(checks: list) -> None:
     """Run the GPU legs' deferred error checks against the oracle."""
     import oracle as O
@@ -648,6 +687,12 @@ def main():
             oracle_checks(checks)
         print(json.dumps(rec))
         return
+    if args.leg == "adjoint":
+        rec = leg_adjoint(args.workload, args.precision, args.steps, args.warmup, checks)
+        if not args.no_cpu:
+            oracle_checks(checks)
+        print(json.dumps(rec))
+        return
     if args.leg == "fig51":
         rec = leg_fig51(checks)
         if not args.no_cpu:
@@ -712,6 +757,8 @@ def main():
         legs["d3_M128_L256_m4_N2M_f64"] = leg_plan("d3_M128_L256_m4_N2M", "f64", short, 2, checks, 3000)
         legs["batched_512_d1_f32"] = leg_batched(short, 2, checks)
         legs["d2_M256_L512_m6_N200k_fwd_bwd_f32"] = leg_differentiation(short, 2)
+        legs["d2_M512_L1024_m5_N1M_adjoint_f32c"] = leg_adjoint(HEADLINE, "f32c", short, 2, checks)
+        legs["d3_M128_L256_m4_N2M_adjoint_f32c"] = leg_adjoint("d3_M128_L256_m4_N2M", "f32c", short, 2, checks)
         legs["d2_M512_L1024_m5_N1M_precomputed_weights"] = leg_precomputed_weights(short, 2, checks)
         legs["d2_M512_L1024_m5_N1M_two_streams"] = leg_two_streams(args.steps, args.warmup, checks)
         legs["example_5_1"] = leg_example51(checks)

@@ -368,7 +368,7 @@ constexpr size_t rows_lds_bytes() {
            sizeof(int) * (48 + rows_batch<R>()) + sizeof(float) * kMaxM * kPolyCoef;
 }
 
-template <typename R, int M2, int METHOD>
+template <typename R, int M2, int METHOD, bool EXACT>
 __global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int m = M2 / 2;
@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
                 R w[2][M2];
                 if constexpr (std::is_same<R, float>::value) {
                     weights_poly<2, M2, kPolyCoef>(theta, coef, w, a.edge_k);
-                } else if (a.use_poly64) {
+                } else if constexpr (!EXACT) {
                     weights_poly64<2, M2, kPolyCoef64>(theta, a.poly64, w, double(a.edge_k));
                 } else {
 #pragma unroll
@@ -525,7 +525,7 @@ constexpr size_t rows3_lds_bytes(int M2) {
            sizeof(int) * (rows_batch<R>() + kRows3Starts) + sizeof(float) * kMaxM * kPolyCoef;
 }
 
-template <typename R, int M2, int METHOD>
+template <typename R, int M2, int METHOD, bool EXACT>
 __global__ void __launch_bounds__(256) k_spread_rows3(SpreadArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int m = M2 / 2;
@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(256) k_spread_rows3(SpreadArgs a) {
             R w[3][M2];
             if constexpr (std::is_same<R, float>::value) {
                 weights_poly<3, M2, kPolyCoef>(theta, coef, w, a.edge_k);
-            } else if (a.use_poly64) {
+            } else if constexpr (!EXACT) {
                 weights_poly64<3, M2, kPolyCoef64>(theta, a.poly64, w, double(a.edge_k));
             } else {
 #pragma unroll
@@ -837,29 +837,29 @@ KFn spread_os_m(int m) {
     }
 }
 
-template <typename R, int METHOD>
+template <typename R, int METHOD, bool EXACT>
 KFn spread_rows_m(int m) {
     switch (m) {
-        case 2: return k_spread_rows<R, 4, METHOD>;
-        case 3: return k_spread_rows<R, 6, METHOD>;
-        case 4: return k_spread_rows<R, 8, METHOD>;
-        case 5: return k_spread_rows<R, 10, METHOD>;
-        case 6: return k_spread_rows<R, 12, METHOD>;
-        case 7: return k_spread_rows<R, 14, METHOD>;
-        case 8: return k_spread_rows<R, 16, METHOD>;
+        case 2: return k_spread_rows<R, 4, METHOD, EXACT>;
+        case 3: return k_spread_rows<R, 6, METHOD, EXACT>;
+        case 4: return k_spread_rows<R, 8, METHOD, EXACT>;
+        case 5: return k_spread_rows<R, 10, METHOD, EXACT>;
+        case 6: return k_spread_rows<R, 12, METHOD, EXACT>;
+        case 7: return k_spread_rows<R, 14, METHOD, EXACT>;
+        case 8: return k_spread_rows<R, 16, METHOD, EXACT>;
         default: return nullptr;
     }
 }
 
-template <typename R, int METHOD>
+template <typename R, int METHOD, bool EXACT>
 KFn spread_rows3_m(int m) {
     switch (m) {
-        case 2: return k_spread_rows3<R, 4, METHOD>;
-        case 3: return k_spread_rows3<R, 6, METHOD>;
-        case 4: return k_spread_rows3<R, 8, METHOD>;
-        case 5: return k_spread_rows3<R, 10, METHOD>;
-        case 6: return k_spread_rows3<R, 12, METHOD>;
-        case 7: return k_spread_rows3<R, 14, METHOD>;
+        case 2: return k_spread_rows3<R, 4, METHOD, EXACT>;
+        case 3: return k_spread_rows3<R, 6, METHOD, EXACT>;
+        case 4: return k_spread_rows3<R, 8, METHOD, EXACT>;
+        case 5: return k_spread_rows3<R, 10, METHOD, EXACT>;
+        case 6: return k_spread_rows3<R, 12, METHOD, EXACT>;
+        case 7: return k_spread_rows3<R, 14, METHOD, EXACT>;
         default: return nullptr;
     }
 }
@@ -941,12 +941,17 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
     const bool use_os = !use_rows && !use_rows3 && box <= int64_t(kp) * kOsThreads && os_lds <= 64 * 1024 &&
                         std::getenv("BL_SPREAD_ATOMIC") == nullptr;
     KFn fn;
+    // Double row kernels with closed-form weights are separate instantiations, so that the
+    // polynomial ones are not register-sized for them.
+    const bool exact = p.prec == BL_F64 && !p.use_poly64;
     if (use_rows) {
-        if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_rows_m<double, 1>(p.m) : spread_rows_m<double, 0>(p.m);
-        else fn = p.method == BL_NFFT ? spread_rows_m<float, 1>(p.m) : spread_rows_m<float, 0>(p.m);
+        if (p.prec != BL_F64) fn = p.method == BL_NFFT ? spread_rows_m<float, 1, false>(p.m) : spread_rows_m<float, 0, false>(p.m);
+        else if (exact) fn = p.method == BL_NFFT ? spread_rows_m<double, 1, true>(p.m) : spread_rows_m<double, 0, true>(p.m);
+        else fn = p.method == BL_NFFT ? spread_rows_m<double, 1, false>(p.m) : spread_rows_m<double, 0, false>(p.m);
     } else if (use_rows3) {
-        if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_rows3_m<double, 1>(p.m) : spread_rows3_m<double, 0>(p.m);
-        else fn = p.method == BL_NFFT ? spread_rows3_m<float, 1>(p.m) : spread_rows3_m<float, 0>(p.m);
+        if (p.prec != BL_F64) fn = p.method == BL_NFFT ? spread_rows3_m<float, 1, false>(p.m) : spread_rows3_m<float, 0, false>(p.m);
+        else if (exact) fn = p.method == BL_NFFT ? spread_rows3_m<double, 1, true>(p.m) : spread_rows3_m<double, 0, true>(p.m);
+        else fn = p.method == BL_NFFT ? spread_rows3_m<double, 1, false>(p.m) : spread_rows3_m<double, 0, false>(p.m);
     } else if (use_os) {
         if (p.prec == BL_F64) fn = p.method == BL_NFFT ? spread_os_d<double, 1>(p.d, p.m) : spread_os_d<double, 0>(p.d, p.m);
         else fn = p.method == BL_NFFT ? spread_os_d<float, 1>(p.d, p.m) : spread_os_d<float, 0>(p.d, p.m);
