@@ -91,7 +91,7 @@ typedef struct {
  *   win    : window: BL_WIN_SINH (eq. (3.4)) or BL_WIN_CKB (continuous Kaiser-Bessel,
  *            Remark 3.1).  The short sums evaluate either through fitted polynomials;
  *            with BL_WIN_CKB an FP64 plan needs its fit within 1e-13 (BL_EUNSUPPORTED
- *            otherwise) and FP64 bl_grad_x is not available.
+ *            otherwise), and FP64 bl_grad_x differentiates the fitted polynomials.
  *   beta   : window parameter; beta <= 0 picks the default: pi*m*(L-M)/L for BL_SHANNON,
  *            2*pi*m*(1 - M/(2L)) for BL_NFFT.
  *   method : BL_SHANNON or BL_NFFT.
@@ -151,9 +151,10 @@ bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev);
 /* Gradient with respect to the nodes: gx[j*d + t] = Re( conj(g_j) * d f_j / d x_jt ),
  * f from the last bl_forward (BL_SHANNON only).  With g = 2(f - y) this is the gradient
  * of sum_j |f_j - y_j|^2.   g_dev : N complex.  gx_dev : N x d real (output).
- * BL_ESTATE if no forward has run since the last bl_set_nodes; BL_EUNSUPPORTED for an
- * FP64 plan with BL_WIN_CKB (its weight derivatives are the sinh window's closed form).
- * Asynchronous. */
+ * BL_ESTATE if no forward has run since the last bl_set_nodes.  FP64 plans with
+ * BL_WIN_CKB take the weight derivatives from the fitted weight polynomials; their
+ * relative deviation from the exact derivatives is checked at plan creation and
+ * BL_EUNSUPPORTED is returned if it exceeds 5e-12.  Asynchronous. */
 bl_status bl_grad_x(bl_plan plan, const void* g_dev, void* gx_dev);
 
 /* Plan statistics.  Synchronous with respect to host state only. */

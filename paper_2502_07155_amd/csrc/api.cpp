@@ -97,11 +97,10 @@ void free_plan(Plan& p) {
     p.use_wpre = false;
 }
 
-// Tile edge per dimension for the short-sum kernels: the staged tile plus halo must fit
-// the LDS budget.
-// Tile edge per dimension: the default edge, shrunk until the staged box (stored twice for
-// float tiles with d >= 2) fits the LDS budget.  The d = 3 budget keeps at least three
-// workgroups per CU (measured: occupancy outweighs the larger halo overhead there).
+// Tile edge per dimension for the short-sum kernels: the default edge, shrunk until the
+// staged tile plus halo (stored twice for float tiles with d >= 2) fits the LDS budget.
+// The d = 3 budget keeps at least three workgroups per CU (measured: occupancy outweighs
+// the larger halo overhead there).
 void choose_tiles(Plan& p) {
     const int d = p.d;
     const size_t budget = (d == 3 ? 44 : 64) * 1024;
@@ -296,6 +295,8 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
             if (p.poly64_err > 1e-13)
                 return cleanup(fail(BL_EUNSUPPORTED, "FP64 weights of this window need a polynomial fit within 1e-13"));
             p.use_poly64 = true;
+            // bl_grad_x differentiates the same polynomials
+            p.poly64_deriv_err = weight_deriv_fit_error(win, method, m, p.beta, kPolyCoef64, p.poly64);
         }
     }
 
@@ -465,8 +466,8 @@ bl_status bl_grad_x(bl_plan plan, const void* g_dev, void* gx_dev) {
     BL_TRY(check_plan(plan));
     Plan& p = plan->p;
     if (p.method != BL_SHANNON) return fail(BL_EUNSUPPORTED, "grad_x is implemented for BL_SHANNON");
-    if (p.prec == BL_F64 && p.win != BL_WIN_SINH)
-        return fail(BL_EUNSUPPORTED, "FP64 grad_x is implemented for the sinh-type window");
+    if (p.prec == BL_F64 && p.win != BL_WIN_SINH && !(p.poly64_deriv_err <= kDerivFitTol))
+        return fail(BL_EUNSUPPORTED, "FP64 grad_x of this window needs weight-polynomial derivatives within 5e-12");
     if (!p.have_theta) return fail(BL_ESTATE, "bl_grad_x needs the samples of a preceding bl_forward");
     if (p.N > 0 && (!g_dev || !gx_dev)) return fail(BL_EINVAL, "NULL buffer");
     return launch_grad_x(p, g_dev, gx_dev);

@@ -36,6 +36,7 @@ constexpr int kMinM = 2;    // truncation range of the compiled short-sum kernel
 constexpr int kMaxM = 8;
 constexpr int kPolyCoef = 12;   // coefficients of the float weight polynomials (degree 11)
 constexpr int kPolyCoef64 = 16; // coefficients of the double weight polynomials (degree 15)
+constexpr double kDerivFitTol = 5e-12;   // FP64 grad_x from differentiated polynomials (relative)
 // Float tiles of the short sums are staged twice (shifted copies, for 128-bit row reads)
 // when the doubled tile still leaves room for several workgroups per CU.
 constexpr bool dual_tiles_for(int d, int m, bool is_float) {
@@ -108,6 +109,7 @@ struct Plan {
     // is within 1e-13 of the exact weights; otherwise the kernels evaluate them exactly.
     std::vector<double> poly64;
     double poly64_err = 0.0;
+    double poly64_deriv_err = 1.0;  // relative error of the polynomials' theta-derivatives
     bool use_poly64 = false;
     double edge_k = 1.0;           // edge exponent of the weight polynomials (edge_exponent)
     bool fft_ok = true;            // L is a power of two >= 16: steps 1-2 and the adjoint available
@@ -185,6 +187,9 @@ void stage_twiddles(const FftFactors& fac, const std::vector<double>& tw, std::v
                     int* off);
 double window_value(bl_window win, bl_method method, int m, double beta, double u);
 double edge_exponent(bl_window win);
+double window_deriv_value(bl_window win, bl_method method, int m, double beta, double u);
+double weight_deriv_fit_error(bl_window win, bl_method method, int m, double beta, int nc,
+                              const std::vector<double>& coef);
 double fit_weight_polys(bl_window win, bl_method method, int m, double beta, int nc,
                         std::vector<double>* coef);
 

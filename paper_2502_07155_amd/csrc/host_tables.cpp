@@ -40,6 +40,18 @@ double bessel_i0(double x) {
     return sum;
 }
 
+// Modified Bessel function I1 by its power series sum (x/2)^{2k+1} / (k! (k+1)!), positive
+// terms as for I0.
+double bessel_i1(double x) {
+    double q = 0.25 * x * x, term = 0.5 * x, sum = term;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / (double(k) * double(k + 1));
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
 // Window in grid units (t = L u) on |t| <= m, given e = m - |t| >= 0 computed without
 // cancellation.  Returns phi_g(t).
 double window_g(bl_window win, int m, double beta, double t_abs, double e) {
@@ -160,6 +172,41 @@ double window_value(bl_window win, bl_method method, int m, double beta, double 
     return v;
 }
 
+// d/du of window_value: phi_g'(u) = phi'(s) ds/du with s = sqrt(1 - (u/m)^2),
+// ds/du = -u / (m^2 s), and sinh(beta s)' = beta cosh(beta s), (I0(beta s))' = beta I1(beta s);
+// for BL_SHANNON times sinc plus sinc'(u) = (cos(pi u) - sinc(u)) / u times the window.
+// At |u| -> m the sinh-type window's derivative is unbounded; callers stay inside.
+double window_deriv_value(bl_window win, bl_method method, int m, double beta, double u) {
+    const double a = std::fabs(u);
+    if (a >= double(m)) return 0.0;
+    const double e = double(m) - a;
+    const double omq = e * (double(m) + a) / (double(m) * double(m));
+    const double s = std::sqrt(omq);
+    const double dsdu = -u / (double(m) * double(m) * s);
+    double phi, dphi;
+    if (win == BL_WIN_SINH) {
+        phi = std::sinh(beta * s) / std::sinh(beta);
+        dphi = beta * std::cosh(beta * s) / std::sinh(beta) * dsdu;
+    } else {
+        const double den = bessel_i0(beta) - 1.0;
+        phi = (bessel_i0(beta * s) - 1.0) / den;
+        // beta I1(beta s) ds/du = -beta^2 u / m^2 * I1(beta s) / (beta s): finite at s = 0
+        const double bs = beta * s;
+        const double i1_over = bs > 1e-8 ? bessel_i1(bs) / bs : 0.5;
+        dphi = -beta * beta * u / (double(m) * double(m)) * i1_over / den;
+    }
+    if (method != BL_SHANNON) return dphi;
+    if (std::fabs(u) < 1e-2) {   // Taylor: sinc and sinc' without the cancellation below
+        const double z2 = kPi * kPi * u * u;
+        const double sc = 1.0 - z2 * (1.0 / 6.0 - z2 / 120.0);
+        const double dsc = -(kPi * kPi * u / 3.0) * (1.0 - z2 * (0.1 - z2 / 280.0));
+        return dsc * phi + sc * dphi;
+    }
+    const double sc = sin_pi(u) / (kPi * u);
+    const double dsc = (cos_pi(u) - sc) / u;
+    return dsc * phi + sc * dphi;
+}
+
 // Edge exponent k of the weight polynomials: the edge pair is sqrt(1 - k theta) K(theta)
 // and sqrt(k theta + 1 - k) K(1 - theta).  The sinh-type window behaves like a square
 // root at the end of its support (k = 1); the continuous Kaiser-Bessel window like
@@ -226,6 +273,47 @@ double fit_weight_polys(bl_window win, bl_method method, int m, double beta, int
         }
     }
     return worst;
+}
+
+// Largest deviation of the derivatives d w_o / d theta of the fitted weights (coefficients
+// as fit_weight_polys stores them, nc per offset) from the exact ones, relative to the
+// largest exact derivative, over all 2m offsets on a grid of theta in [0, 1].  The sinh
+// window's edge factor has an unbounded derivative at the support end; the check is meant
+// for windows with edge exponent 0.
+double weight_deriv_fit_error(bl_window win, bl_method method, int m, double beta, int nc,
+                              const std::vector<double>& coef) {
+    const int n = nc;
+    const double k = edge_exponent(win);
+    double worst = 0.0, scale = 0.0;
+    std::vector<double> mono(n);
+    for (int o = 0; o < m; ++o) {
+        for (int j = 0; j < n; ++j) mono[j] = coef[size_t(o) * nc + (j % 2 == 0 ? j / 2 : n / 2 + j / 2)];
+        for (int qi = 1; qi < 512; ++qi) {
+            const double th = qi / 512.0;
+            for (int side = 0; side < 2; ++side) {
+                // w_o(theta) = P(theta - 1/2), w_{2m-1-o}(theta) = P(1/2 - theta) (times the
+                // edge factor for o = 0)
+                const double t = side == 0 ? th - 0.5 : 0.5 - th;
+                const double sgn = side == 0 ? 1.0 : -1.0;
+                double P = 0.0, dP = 0.0;
+                for (int j = n - 1; j >= 0; --j) {
+                    dP = dP * t + P;
+                    P = P * t + mono[j];
+                }
+                double dw = sgn * dP;
+                if (o == 0 && k != 0.0) {
+                    const double f = side == 0 ? 1.0 - k * th : k * th + 1.0 - k;
+                    const double sf = std::sqrt(f);
+                    dw = sf * dw + (side == 0 ? -k : k) * P / (2.0 * sf);
+                }
+                const int oo = side == 0 ? o : 2 * m - 1 - o;
+                const double ex = window_deriv_value(win, method, m, beta, th + (m - 1 - oo));
+                worst = std::max(worst, std::fabs(dw - ex));
+                scale = std::max(scale, std::fabs(ex));
+            }
+        }
+    }
+    return scale > 0.0 ? worst / scale : worst;
 }
 
 // Per-stage twiddles w^{r k} = e^{2 pi i r k / (Ns R)}, laid out [k][r-1] for each stage

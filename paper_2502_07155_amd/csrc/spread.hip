@@ -668,7 +668,54 @@ __global__ void __launch_bounds__(256) k_spread_rows3(SpreadArgs a) {
     });
 }
 
-template <typename R, int D, int M2>
+// Double weights and their theta-derivatives from the double weight polynomials (layout
+// of weights_poly64: per offset o, even then odd monomial coefficients in t = theta - 1/2;
+// w_o = P_o(t), w_{2m-1-o} = P_o(-t), the edge pair times sqrt(1 - k theta) and
+// sqrt(k theta + 1 - k)).  Used for windows without an exact device formula.
+template <int D, int M2, int NC>
+__device__ __forceinline__ void weights_poly64_deriv(const double* theta, const double* coef,
+                                                     double (*w)[M2], double (*dw)[M2], double ek) {
+    constexpr int m = M2 / 2;
+    constexpr int NE = NC / 2;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double t = theta[d] - 0.5, t2 = t * t;
+#pragma unroll
+        for (int o = 0; o < m; ++o) {
+            const double* c = coef + o * NC;
+            double E = c[NE - 1], Od = c[NC - 1], dE = 0.0, dO = 0.0;
+#pragma unroll
+            for (int k = NE - 2; k >= 0; --k) {
+                dE = fma(dE, t2, E);
+                E = fma(E, t2, c[k]);
+                dO = fma(dO, t2, Od);
+                Od = fma(Od, t2, c[NE + k]);
+            }
+            // p(t) = E + t O, q(t) = p(-t); dp/dtheta = A + B, dq/dtheta = A - B
+            const double tO = t * Od;
+            const double A = 2.0 * t * dE, B = fma(2.0 * t2, dO, Od);
+            const double p = E + tO, q = E - tO, dp = A + B, dq = A - B;
+            if (o == 0) {
+                const double s1 = sqrt(fma(-ek, theta[d], 1.0));
+                const double s0 = sqrt(fma(ek, theta[d], 1.0 - ek));
+                w[d][0] = s1 * p;
+                dw[d][0] = ek != 0.0 ? fma(s1, dp, -0.5 * ek * p / s1) : dp;
+                w[d][M2 - 1] = s0 * q;
+                dw[d][M2 - 1] = ek != 0.0 ? (s0 > 0.0 ? fma(s0, dq, 0.5 * ek * q / s0) : 0.0) : dq;
+            } else {
+                w[d][o] = p;
+                w[d][M2 - 1 - o] = q;
+                dw[d][o] = dp;
+                dw[d][M2 - 1 - o] = dq;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// DPOLY (double only): weights and derivatives from the double weight polynomials
+// (windows without an exact device formula) instead of the sinh window's closed form.
+template <typename R, int D, int M2, bool DPOLY>
 __global__ void __launch_bounds__(256) k_grad_x(SpreadArgs a) {
     extern __shared__ unsigned char smem_raw[];
     Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
@@ -718,6 +765,8 @@ __global__ void __launch_bounds__(256) k_grad_x(SpreadArgs a) {
         }
         if constexpr (std::is_same<R, float>::value) {
             weights_poly_deriv<D, M2, kPolyCoef>(theta, coef, w, dw, a.edge_k);
+        } else if constexpr (DPOLY) {
+            weights_poly64_deriv<D, M2, kPolyCoef64>(theta, a.poly64, w, dw, double(a.edge_k));
         } else {
 #pragma unroll
             for (int t = 0; t < D; ++t) weights_and_derivs<R, M2>(theta[t], beta, cb, inv_m2, w[t], dw[t]);
@@ -809,16 +858,16 @@ KFn spread_m(int m) {
     }
 }
 
-template <typename R, int D>
+template <typename R, int D, bool DPOLY>
 KFn grad_m(int m) {
     switch (m) {
-        case 2: return k_grad_x<R, D, 4>;
-        case 3: return k_grad_x<R, D, 6>;
-        case 4: return k_grad_x<R, D, 8>;
-        case 5: return k_grad_x<R, D, 10>;
-        case 6: return k_grad_x<R, D, 12>;
-        case 7: return k_grad_x<R, D, 14>;
-        case 8: return k_grad_x<R, D, 16>;
+        case 2: return k_grad_x<R, D, 4, DPOLY>;
+        case 3: return k_grad_x<R, D, 6, DPOLY>;
+        case 4: return k_grad_x<R, D, 8, DPOLY>;
+        case 5: return k_grad_x<R, D, 10, DPOLY>;
+        case 6: return k_grad_x<R, D, 12, DPOLY>;
+        case 7: return k_grad_x<R, D, 14, DPOLY>;
+        case 8: return k_grad_x<R, D, 16, DPOLY>;
         default: return nullptr;
     }
 }
@@ -880,11 +929,11 @@ KFn spread_d(int d, int m) {
     return nullptr;
 }
 
-template <typename R>
+template <typename R, bool DPOLY>
 KFn grad_d(int d, int m) {
-    if (d == 1) return grad_m<R, 1>(m);
-    if (d == 2) return grad_m<R, 2>(m);
-    if (d == 3) return grad_m<R, 3>(m);
+    if (d == 1) return grad_m<R, 1, DPOLY>(m);
+    if (d == 2) return grad_m<R, 2, DPOLY>(m);
+    if (d == 3) return grad_m<R, 3, DPOLY>(m);
     return nullptr;
 }
 
@@ -975,7 +1024,9 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
 
 bl_status launch_grad_x(Plan& p, const void* g, void* gx) {
     if (p.N == 0 || p.nchunks == 0) return BL_OK;
-    KFn fn = (p.prec == BL_F64) ? grad_d<double>(p.d, p.m) : grad_d<float>(p.d, p.m);
+    // FP64: the sinh window's closed form, else (checked at bl_grad_x) the polynomials'
+    KFn fn = p.prec != BL_F64 ? grad_d<float, false>(p.d, p.m)
+             : p.win == BL_WIN_SINH ? grad_d<double, false>(p.d, p.m) : grad_d<double, true>(p.d, p.m);
     if (!fn) {
         set_error("no gradient kernel for this (d, m)");
         return BL_EUNSUPPORTED;

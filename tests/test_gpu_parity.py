@@ -399,27 +399,20 @@ def test_ckb_adjoint_matches_oracle(d, M, L, m, N, prec, method):
     assert O.rel_err_inf(a, ao) <= (1e-12 if prec == "f64" else 1e-5)
 
 
-@pytest.mark.parametrize("d,M,L,m,N", CKB)
-def test_ckb_grad_x_matches_oracle(d, M, L, m, N):
-    p = W.custom_problem(d, M, L, m, N, seed=800 + d + m, precision="f32", with_targets=True)
-    plan = ckb_plan(p, "f32")
-    plan.set_nodes(dev_real(p.x, "f32"))
-    f = plan.forward(dev_cplx(p.fhat, "f32"))
-    G = 2 * (f - dev_cplx(p.y, "f32"))
+@pytest.mark.parametrize("d,M,L,m,N", CKB + [(2, 64, 128, 2, 3000)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ckb_grad_x_matches_oracle(d, M, L, m, N, prec):
+    """FP32 from the float weight polynomials' derivatives; FP64 from the double ones (the
+    cKB window has no closed form in the device code).  m = 2 has the largest derivative
+    fit error of the tested cases (1.8e-12 relative)."""
+    p = W.custom_problem(d, M, L, m, N, seed=800 + d + m, precision=prec, with_targets=True)
+    plan = ckb_plan(p, prec)
+    plan.set_nodes(dev_real(p.x, prec))
+    f = plan.forward(dev_cplx(p.fhat, prec))
+    G = 2 * (f - dev_cplx(p.y, prec))
     gx = host(plan.grad_x(G))
     go = O.grad_x_shannon(p.fhat, host(G), p.x, L, m, win="ckb")
-    assert O.rel_err_inf(gx, go) <= 2e-5
-
-
-def test_ckb_fp64_grad_x_is_refused():
-    from paper_2502_07155_amd._lib import BLNFFTError
-    p = W.custom_problem(2, 32, 64, 4, 500, seed=9, precision="f64", with_targets=True)
-    plan = ckb_plan(p, "f64")
-    plan.set_nodes(dev_real(p.x, "f64"))
-    f = plan.forward(dev_cplx(p.fhat, "f64"))
-    with pytest.raises(BLNFFTError) as e:
-        plan.grad_x(f)
-    assert e.value.status == 6
+    assert O.rel_err_inf(gx, go) <= (1e-11 if prec == "f64" else 2e-5)
 
 
 @pytest.mark.parametrize("d,M,L,m,N", [(1, 64, 128, 5, 3000), (2, 64, 128, 5, 5000),
