@@ -244,7 +244,8 @@ def test_adjoint_matches_oracle(d, M, L, m, N, prec, method):
 @pytest.mark.parametrize("d,M,L,m,N,tile", [(1, 64, 128, 5, 1500, None), (2, 32, 64, 6, 40000, None),
                                             (2, 64, 128, 8, 5000, None), (2, 64, 128, 4, 5000, 24),
                                             (3, 16, 32, 3, 1500, None), (3, 16, 32, 3, 40000, None),
-                                            (3, 32, 64, 4, 12000, None), (3, 32, 64, 2, 12000, 11)])
+                                            (3, 32, 64, 4, 12000, None), (3, 32, 64, 2, 12000, 11),
+                                            (3, 16, 32, 7, 2000, None)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("kernel", ["default", "BL_SPREAD_OS", "BL_SPREAD_ATOMIC"])
 def test_adjoint_spread_kernels(d, M, L, m, N, tile, prec, kernel, monkeypatch):
@@ -252,7 +253,7 @@ def test_adjoint_spread_kernels(d, M, L, m, N, tile, prec, kernel, monkeypatch):
     LDS-atomic kernel) against the oracle, with several node batches per chunk (N = 40000
     puts about 2500 nodes in each of 16 tiles in d = 2, 625 in each of 64 in d = 3, so
     also several chunks per tile), boxes that do not fit the d = 2 row kernel (tile 24),
-    and d = 3 boxes of 14^3 (m = 4, tile 7; m = 2, tile 11)."""
+    and d = 3 boxes of 14^3 (m = 4, tile 7; m = 2, tile 11; FP64 m = 7, tile 1)."""
     if kernel != "default":
         monkeypatch.setenv(kernel, "1")
     if tile is not None:
