@@ -112,6 +112,16 @@ def time_calls(torch, fn, steps: int, warmup: int, stream) -> float:
     return start.elapsed_time(end) / steps
 
 
+def copy_bandwidth(torch, nbytes: int = 1 << 28, reps: int = 20) -> float:
+    """Measured HBM bandwidth of a plain device copy (bytes read + written per second, GB/s),
+    the achievable figure beside the nominal peak."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ms = time_calls(torch, lambda: b.copy_(a), reps, 3, torch.cuda.current_stream())
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def source_digest(paths) -> str:
     h = hashlib.sha256()
     for p in paths:
@@ -743,7 +753,9 @@ def main():
                      "per_node_flops_contraction_only": mac_flops_per_node(p.d, p.m),
                      "frac_contraction_only": mac_flops_per_node(p.d, p.m) * p.N / (gms * 1e-3) / 1e12 / peak},
         "hbm": {"algorithmic_bytes": ab, "deconv_fft_GBs": ab["fft"] / (fft_ms * 1e-3) / 1e9,
-                "gather_GBs": ab["gather"] / (gms * 1e-3) / 1e9, "peak_GBs": HBM_PEAK_GBS},
+                "gather_GBs": ab["gather"] / (gms * 1e-3) / 1e9, "peak_GBs": HBM_PEAK_GBS,
+                "copy_GBs": copy_bandwidth(torch),
+                "copy_note": "device-to-device copy of 256 MiB, read + write bytes per second"},
     }
     plan.close()
     checks.append(accuracy_check(rec, p, f, key="rel_err", l2=True))
