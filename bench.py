@@ -754,8 +754,9 @@ def main():
                      "frac_contraction_only": mac_flops_per_node(p.d, p.m) * p.N / (gms * 1e-3) / 1e12 / peak},
         "hbm": {"algorithmic_bytes": ab, "deconv_fft_GBs": ab["fft"] / (fft_ms * 1e-3) / 1e9,
                 "gather_GBs": ab["gather"] / (gms * 1e-3) / 1e9, "peak_GBs": HBM_PEAK_GBS,
-                "copy_GBs": copy_bandwidth(torch),
-                "copy_note": "device-to-device copy of 256 MiB, read + write bytes per second"},
+                "copy_GBs": None if args.headline_only else copy_bandwidth(torch),
+                "copy_note": "device-to-device copy of 256 MiB, read + write bytes per second "
+                             "(full runs only, so that profiles of --headline-only stay clean)"},
     }
     plan.close()
     checks.append(accuracy_check(rec, p, f, key="rel_err", l2=True))
