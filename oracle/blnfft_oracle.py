@@ -15,7 +15,7 @@ Notation (paper, Sections 1-4): d dimensions, bandwidth M (even), oversampled gr
 nodes x_j in [-1/2, 1/2)^d.  Arrays over I_M or I_L are stored centred: array index
 i_t holds k_t = i_t - M/2 (or l_t = i_t - L/2).
 
-Readings of points the paper leaves open (each is listed in the design doc as well):
+Readings of points the paper leaves open:
 * The d-variate window is the tensor product of the univariate one, so psi and its
   transform factor over dimensions.
 * L must be even (I_L is defined like I_M, which needs an even size).
