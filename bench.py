@@ -758,6 +758,15 @@ def main():
                 "copy_note": "device-to-device copy of 256 MiB, read + write bytes per second "
                              "(full runs only, so that profiles of --headline-only stay clean)"},
     }
+    # steady-state rebinding of the same nodes (a training loop that moves x pays this per step)
+    xr = torch.from_numpy(p.x).to(torch.float64 if prec == "f64" else torch.float32).cuda()
+    plan.set_nodes(xr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        plan.set_nodes(xr)
+    torch.cuda.synchronize()
+    rec["rebind_ms"] = (time.perf_counter() - t0) * 1e3 / 5
     plan.close()
     checks.append(accuracy_check(rec, p, f, key="rel_err", l2=True))
     if not args.headline_only and args.workload == HEADLINE and prec != "f64":
