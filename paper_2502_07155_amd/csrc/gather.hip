@@ -57,46 +57,34 @@ __device__ __forceinline__ int node_tile_of(const BinArgs& a, const R* x, int64_
     return tile;
 }
 
-template <typename R, int D>
-__global__ void k_bin_count(BinArgs a) {
-    int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= a.N) return;
-    bool bad, outside;
-    const int tile = node_tile_of<R, D>(a, static_cast<const R*>(a.x), j, bad, outside);
-    if (bad) atomicAdd(&a.flags[0], 1ull);
-    if (outside) atomicAdd(&a.flags[1], 1ull);
-    a.node_tile[j] = tile;
-    atomicAdd(&a.tile_count[tile], 1);
-}
-
-// Binning with per-workgroup LDS histograms, for plans with at most kLdsBins tiles.  A
-// workgroup takes kBinPer * kBinThreads consecutive nodes and counts them per tile in LDS,
-// then adds each nonzero count to the global counter once (instead of one contended global
-// atomic per node); the domain flags are summed per wave first.  The scatter recounts the
-// same nodes, keeping each node's LDS rank, reserves one range per tile with a single
-// global atomic and places every node at its rank in that range.
+// Binning with per-workgroup LDS histograms.  A workgroup takes kBinPer * kBinThreads
+// consecutive nodes (their tiles stay in registers) and walks the tiles in windows of
+// kLdsBins: it counts its nodes of the window in LDS, then adds each nonzero count to the
+// global counter once, instead of one contended global atomic per node.  The domain flags
+// are summed per wave first.  The scatter recounts the same nodes window by window, keeping
+// each node's LDS rank, reserves one range per tile with a single global atomic and places
+// every node at its rank in that range.
 constexpr int kLdsBins = 8192;
 constexpr int kBinThreads = 256;
 constexpr int kBinPer = 16;
 
 template <typename R, int D>
-__global__ void __launch_bounds__(kBinThreads) k_bin_count_lds(BinArgs a, int ntiles) {
+__global__ void __launch_bounds__(kBinThreads) k_bin_count(BinArgs a, int ntiles) {
     __shared__ int hist[kLdsBins];
-    for (int e = threadIdx.x; e < ntiles; e += kBinThreads) hist[e] = 0;
-    __syncthreads();
     const R* x = static_cast<const R*>(a.x);
     const int64_t j0 = int64_t(blockIdx.x) * (kBinThreads * kBinPer) + threadIdx.x;
+    int tl[kBinPer];
     int nbad = 0, nout = 0;
-#pragma unroll 4
+#pragma unroll
     for (int k = 0; k < kBinPer; ++k) {
         const int64_t j = j0 + int64_t(k) * kBinThreads;
+        tl[k] = -1;
         if (j < a.N) {
             bool bad, outside;
-            const int tile = node_tile_of<R, D>(a, x, j, bad, outside);
+            tl[k] = node_tile_of<R, D>(a, x, j, bad, outside);
             nbad += bad ? 1 : 0;
             nout += outside ? 1 : 0;
-            a.node_tile[j] = tile;
-            atomicAdd(&hist[tile], 1);
+            a.node_tile[j] = tl[k];
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -107,9 +95,20 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_count_lds(BinArgs a, int nt
         if (nbad) atomicAdd(&a.flags[0], (unsigned long long)nbad);
         if (nout) atomicAdd(&a.flags[1], (unsigned long long)nout);
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < ntiles; e += kBinThreads)
-        if (hist[e]) atomicAdd(&a.tile_count[e], hist[e]);
+    for (int w0 = 0; w0 < ntiles; w0 += kLdsBins) {
+        const int nw = min(kLdsBins, ntiles - w0);
+        __syncthreads();   // previous window flushed
+        for (int e = threadIdx.x; e < nw; e += kBinThreads) hist[e] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kBinPer; ++k) {
+            const int e = tl[k] - w0;
+            if (tl[k] >= 0 && e >= 0 && e < nw) atomicAdd(&hist[e], 1);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nw; e += kBinThreads)
+            if (hist[e]) atomicAdd(&a.tile_count[w0 + e], hist[e]);
+    }
 }
 
 // One workgroup: exclusive scans of node counts and of chunk counts per tile.
@@ -148,53 +147,46 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int32_t* count, int32_
 }
 
 template <typename R, int D>
-__global__ void k_bin_scatter(const R* __restrict__ x, int64_t N, const int32_t* node_tile,
-                              const int32_t* offset, int32_t* cursor, int32_t* perm,
-                              R* __restrict__ xs) {
-    int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    int tile = node_tile[j];
-    int pos = offset[tile] + atomicAdd(&cursor[tile], 1);
-    perm[pos] = int32_t(j);
-#pragma unroll
-    for (int t = 0; t < D; ++t) xs[int64_t(pos) * D + t] = x[j * D + t];
-}
-
-template <typename R, int D>
-__global__ void __launch_bounds__(kBinThreads) k_bin_scatter_lds(const R* __restrict__ x, int64_t N,
-                                                                 const int32_t* node_tile,
-                                                                 const int32_t* offset, int32_t* cursor,
-                                                                 int32_t* perm, R* __restrict__ xs,
-                                                                 int ntiles) {
+__global__ void __launch_bounds__(kBinThreads) k_bin_scatter(const R* __restrict__ x, int64_t N,
+                                                             const int32_t* node_tile,
+                                                             const int32_t* offset, int32_t* cursor,
+                                                             int32_t* perm, R* __restrict__ xs,
+                                                             int ntiles) {
     __shared__ int hist[kLdsBins];   // counts, then the start of this workgroup's range
-    for (int e = threadIdx.x; e < ntiles; e += kBinThreads) hist[e] = 0;
-    __syncthreads();
     const int64_t j0 = int64_t(blockIdx.x) * (kBinThreads * kBinPer) + threadIdx.x;
     int tl[kBinPer], rank[kBinPer];
 #pragma unroll
     for (int k = 0; k < kBinPer; ++k) {
         const int64_t j = j0 + int64_t(k) * kBinThreads;
-        tl[k] = -1;
+        tl[k] = j < N ? node_tile[j] : -1;
         rank[k] = 0;
-        if (j < N) {
-            tl[k] = node_tile[j];
-            rank[k] = atomicAdd(&hist[tl[k]], 1);
+    }
+    for (int w0 = 0; w0 < ntiles; w0 += kLdsBins) {
+        const int nw = min(kLdsBins, ntiles - w0);
+        __syncthreads();   // previous window placed
+        for (int e = threadIdx.x; e < nw; e += kBinThreads) hist[e] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kBinPer; ++k) {
+            const int e = tl[k] - w0;
+            if (tl[k] >= 0 && e >= 0 && e < nw) rank[k] = atomicAdd(&hist[e], 1);
         }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < ntiles; e += kBinThreads) {
-        const int c = hist[e];
-        if (c) hist[e] = offset[e] + atomicAdd(&cursor[e], c);
-    }
-    __syncthreads();
+        __syncthreads();
+        for (int e = threadIdx.x; e < nw; e += kBinThreads) {
+            const int c = hist[e];
+            if (c) hist[e] = offset[w0 + e] + atomicAdd(&cursor[w0 + e], c);
+        }
+        __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kBinPer; ++k) {
-        if (tl[k] < 0) continue;
-        const int64_t j = j0 + int64_t(k) * kBinThreads;
-        const int pos = hist[tl[k]] + rank[k];
-        perm[pos] = int32_t(j);
+        for (int k = 0; k < kBinPer; ++k) {
+            const int e = tl[k] - w0;
+            if (tl[k] < 0 || e < 0 || e >= nw) continue;
+            const int64_t j = j0 + int64_t(k) * kBinThreads;
+            const int pos = hist[e] + rank[k];
+            perm[pos] = int32_t(j);
 #pragma unroll
-        for (int t = 0; t < D; ++t) xs[int64_t(pos) * D + t] = x[j * D + t];
+            for (int t = 0; t < D; ++t) xs[int64_t(pos) * D + t] = x[j * D + t];
+        }
     }
 }
 
@@ -702,65 +694,37 @@ bl_status launch_binning(Plan& p, const void* x, int64_t N) {
     a.node_tile = p.d_node_tile;
     a.tile_count = p.d_tile_count;
     a.flags = p.d_flags;
-    const unsigned nb = unsigned((N + 255) / 256);
     const bool dbl = p.prec == BL_F64;
-    // LDS histograms when the tile counters fit (d <= 2 workloads); else one atomic per node
-    const bool lds_bins = p.ntiles <= kLdsBins;
     const unsigned nbl = unsigned((N + kBinThreads * kBinPer - 1) / (kBinThreads * kBinPer));
     const int nt = int(p.ntiles);
     if (N > 0) {
-        if (lds_bins) {
-            if (dbl) {
-                if (p.d == 1) hipLaunchKernelGGL((k_bin_count_lds<double, 1>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
-                if (p.d == 2) hipLaunchKernelGGL((k_bin_count_lds<double, 2>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
-                if (p.d == 3) hipLaunchKernelGGL((k_bin_count_lds<double, 3>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
-            } else {
-                if (p.d == 1) hipLaunchKernelGGL((k_bin_count_lds<float, 1>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
-                if (p.d == 2) hipLaunchKernelGGL((k_bin_count_lds<float, 2>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
-                if (p.d == 3) hipLaunchKernelGGL((k_bin_count_lds<float, 3>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
-            }
-        } else if (dbl) {
-            if (p.d == 1) hipLaunchKernelGGL((k_bin_count<double, 1>), dim3(nb), dim3(256), 0, p.stream, a);
-            if (p.d == 2) hipLaunchKernelGGL((k_bin_count<double, 2>), dim3(nb), dim3(256), 0, p.stream, a);
-            if (p.d == 3) hipLaunchKernelGGL((k_bin_count<double, 3>), dim3(nb), dim3(256), 0, p.stream, a);
+        if (dbl) {
+            if (p.d == 1) hipLaunchKernelGGL((k_bin_count<double, 1>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
+            if (p.d == 2) hipLaunchKernelGGL((k_bin_count<double, 2>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
+            if (p.d == 3) hipLaunchKernelGGL((k_bin_count<double, 3>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
         } else {
-            if (p.d == 1) hipLaunchKernelGGL((k_bin_count<float, 1>), dim3(nb), dim3(256), 0, p.stream, a);
-            if (p.d == 2) hipLaunchKernelGGL((k_bin_count<float, 2>), dim3(nb), dim3(256), 0, p.stream, a);
-            if (p.d == 3) hipLaunchKernelGGL((k_bin_count<float, 3>), dim3(nb), dim3(256), 0, p.stream, a);
+            if (p.d == 1) hipLaunchKernelGGL((k_bin_count<float, 1>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
+            if (p.d == 2) hipLaunchKernelGGL((k_bin_count<float, 2>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
+            if (p.d == 3) hipLaunchKernelGGL((k_bin_count<float, 3>), dim3(nbl), dim3(kBinThreads), 0, p.stream, a, nt);
         }
         BL_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, p.stream, p.d_tile_count,
                        p.d_tile_offset, p.d_chunk_offset, p.ntiles, p.chunk_cap, p.d_flags);
     BL_HIP(hipGetLastError());
-    if (N > 0 && lds_bins) {
+    if (N > 0) {
         if (dbl) {
             const double* xd = static_cast<const double*>(x);
             double* xs = static_cast<double*>(p.d_xs);
-            if (p.d == 1) hipLaunchKernelGGL((k_bin_scatter_lds<double, 1>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
-            if (p.d == 2) hipLaunchKernelGGL((k_bin_scatter_lds<double, 2>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
-            if (p.d == 3) hipLaunchKernelGGL((k_bin_scatter_lds<double, 3>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
+            if (p.d == 1) hipLaunchKernelGGL((k_bin_scatter<double, 1>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
+            if (p.d == 2) hipLaunchKernelGGL((k_bin_scatter<double, 2>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
+            if (p.d == 3) hipLaunchKernelGGL((k_bin_scatter<double, 3>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
         } else {
             const float* xf = static_cast<const float*>(x);
             float* xs = static_cast<float*>(p.d_xs);
-            if (p.d == 1) hipLaunchKernelGGL((k_bin_scatter_lds<float, 1>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
-            if (p.d == 2) hipLaunchKernelGGL((k_bin_scatter_lds<float, 2>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
-            if (p.d == 3) hipLaunchKernelGGL((k_bin_scatter_lds<float, 3>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
-        }
-        BL_HIP(hipGetLastError());
-    } else if (N > 0) {
-        if (dbl) {
-            const double* xd = static_cast<const double*>(x);
-            double* xs = static_cast<double*>(p.d_xs);
-            if (p.d == 1) hipLaunchKernelGGL((k_bin_scatter<double, 1>), dim3(nb), dim3(256), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
-            if (p.d == 2) hipLaunchKernelGGL((k_bin_scatter<double, 2>), dim3(nb), dim3(256), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
-            if (p.d == 3) hipLaunchKernelGGL((k_bin_scatter<double, 3>), dim3(nb), dim3(256), 0, p.stream, xd, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
-        } else {
-            const float* xf = static_cast<const float*>(x);
-            float* xs = static_cast<float*>(p.d_xs);
-            if (p.d == 1) hipLaunchKernelGGL((k_bin_scatter<float, 1>), dim3(nb), dim3(256), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
-            if (p.d == 2) hipLaunchKernelGGL((k_bin_scatter<float, 2>), dim3(nb), dim3(256), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
-            if (p.d == 3) hipLaunchKernelGGL((k_bin_scatter<float, 3>), dim3(nb), dim3(256), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs);
+            if (p.d == 1) hipLaunchKernelGGL((k_bin_scatter<float, 1>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
+            if (p.d == 2) hipLaunchKernelGGL((k_bin_scatter<float, 2>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
+            if (p.d == 3) hipLaunchKernelGGL((k_bin_scatter<float, 3>), dim3(nbl), dim3(kBinThreads), 0, p.stream, xf, N, p.d_node_tile, p.d_tile_offset, p.d_tile_cursor, p.d_perm, xs, nt);
         }
         BL_HIP(hipGetLastError());
     }
