@@ -30,9 +30,15 @@ sys.path.insert(0, ROOT)
 METRIC = "node evals/sec at rel err 1e-6 (FP32c) vs 1e-12 (FP64); % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 # Vector FP32 without packed instructions (the library is built without them) issues like
-# FP64: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s.
+# FP64: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s.  The
+# published vector FP32 figure, 157.3 TFLOP/s, counts packed (two-wide) FP32 FMAs.
 FP32_PEAK_TFLOPS = 78.6
 FP64_PEAK_TFLOPS = 78.6
+FP32_PUBLISHED_TFLOPS = 157.3
+PEAK_BASIS = ("alu peak from unit counts and clock: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) "
+              "x 2.4 GHz = 78.6 TFLOP/s, the non-packed FP32 (and FP64) vector rate; packed FP32 "
+              "instructions are disabled in this build, so the published 157.3 TFLOP/s (packed "
+              "FP32) is out of reach by construction; frac_vs_published divides by it")
 GATHER_SOURCES = ["paper_2502_07155_amd/csrc/gather.hip", "paper_2502_07155_amd/csrc/device_math.h"]
 TRAFFIC_FILE = "profiles/k_gather_d2_M512_L1024_m5_N1M_f32c_traffic.txt"
 HEADLINE = "d2_M512_L1024_m5_N1M"
@@ -44,7 +50,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=HEADLINE)
-    ap.add_argument("--precision", default="f32c", choices=["f32c", "f32", "f64"])
+    ap.add_argument("--precision", default="f32c", choices=["f32c", "f32d", "f32", "f64"])
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline workload only (no other legs, no CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true",
@@ -63,8 +69,12 @@ def parse():
                          "csv output directory and exit (no GPU use)")
     ap.add_argument("--summarize-traffic", nargs=4,
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
-                    help="print the gather's HBM traffic per launch from four rocprofv3 --pmc "
+                    help="print a kernel's HBM traffic per launch from four rocprofv3 --pmc "
                          "csv output directories and exit (no GPU use)")
+    ap.add_argument("--traffic-kernel", default="gather", choices=["gather", "fft"],
+                    help="with --summarize-traffic: the gather, or the FFT passes of a transform")
+    ap.add_argument("--traffic-passes", type=int, default=1,
+                    help="with --summarize-traffic: dispatches per launch (FFT: one per dimension)")
     return ap.parse_args()
 
 
@@ -144,6 +154,23 @@ def measured_traffic():
     return float(val.group(1))
 
 
+FFT_SOURCES = ["paper_2502_07155_amd/csrc/fft.hip", "paper_2502_07155_amd/csrc/stockham.h"]
+
+
+def measured_fft_traffic(workload: str, prec: str):
+    """HBM bytes per transform (all passes) from the committed counter summary of this
+    workload and precision, if it was taken on the current FFT sources; else None."""
+    path = os.path.join(ROOT, f"profiles/k_fft_pass_{workload}_{prec}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    sha = re.search(r"^source_sha256:\s*(\w+)", text, re.M)
+    val = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", text, re.M)
+    if not sha or not val or sha.group(1) != source_digest(FFT_SOURCES):
+        return None
+    return float(val.group(1))
+
+
 # ---------------------------------------------------------------- legs
 def run_plan(name: str, prec: str, steps: int, warmup: int, method: str = "shannon", beta: float = 0.0):
     import numpy as np
@@ -169,7 +196,11 @@ def run_plan(name: str, prec: str, steps: int, warmup: int, method: str = "shann
     theta = plan.theta()
     gout = torch.empty_like(out)
     gms = time_calls(torch, lambda: plan.interpolate(theta, out=gout), steps, warmup, stream)
+    # steps 1-2 alone (the FFT passes), for the transform's own roofline entry
+    fms = time_calls(torch, lambda: plan.samples(fhat), steps, warmup, stream)
+    plan.forward(fhat, out=out)   # the plan's samples are those of this forward again
     f = out.cpu().numpy().astype(np.complex128)
+    plan.fft_ms = fms
     return p, plan, f, ms, gms, plan_ms
 
 
@@ -236,8 +267,7 @@ def leg_plan(name, prec, steps, warmup, checks: list, sample=5000):
 
 # Example 5.1 (Section 5): f(x) = sinc^2(M pi x / 2) with the triangle fhat, N = M/2
 # Chebyshev nodes (5.6), m = 5, L = 2M, error max_j |f_j - f(x_j)| (5.5).
-EXAMPLE51_M_PAPER = [20, 40, 80, 160, 320, 640, 1000]
-EXAMPLE51_M_POW2 = [16, 32, 64, 128, 256, 512, 1024]
+EXAMPLE51_M_PAPER = list(range(20, 1001, 20))   # M in {20, 40, ..., 1000}, Example 5.1
 
 
 def example51_inputs(M: int, m: int = 5):
@@ -251,19 +281,20 @@ def example51_inputs(M: int, m: int = 5):
 
 
 def leg_example51(checks: list):
-    """Example 5.1 on the GPU.  Per-plan FP64 (power-of-two L: M = 16..1024) for Algorithm
-    4.2 and Algorithm 2.1 with both beta readings (the same beta as Algorithm 4.2, and the
-    standard NFFT beta); the batched FP32 path (any even L) at the paper's M = 20..1000 for
-    Algorithm 4.2.  Parity of every run with the oracle is filled in by the oracle leg."""
+    """Example 5.1 on the GPU at the paper's M = 20, 40, ..., 1000 (L = 2M, steps 1-2 by the
+    chirp-z passes where L is not a power of two): per-plan FP64 for Algorithm 4.2 and
+    Algorithm 2.1 with both beta readings (the same beta as Algorithm 4.2, and the standard
+    NFFT beta), and the batched FP32 path for Algorithm 4.2.  Parity of every run with the
+    oracle is filled in by the oracle leg; the 50-row table goes to stderr."""
     import numpy as np
     import torch
 
     from paper_2502_07155_amd import BatchPlan, Plan
     m = 5
-    out = {"m": m, "per_plan_f64": {}, "batched_f32": {}}
-    for M in EXAMPLE51_M_POW2:
+    out = {"m": m, "M_values": EXAMPLE51_M_PAPER, "per_plan_f64": {}, "batched_f32": {}}
+    for M in EXAMPLE51_M_PAPER:
         L, x, fhat, exact = example51_inputs(M, m)
-        row = {}
+        row = {"L": L}
         runs = (("alg4_2", "shannon", 0.0), ("alg2_1_same_beta", "nfft", None),
                 ("alg2_1_standard_beta", "nfft", 0.0))
         beta_shannon = None
@@ -283,6 +314,10 @@ def leg_example51(checks: list):
                 rec["rel_err_vs_oracle"] = O.rel_err_inf(f, fn(fhat, x[:, None], L, m, beta))
             checks.append(check)
         out["per_plan_f64"][str(M)] = row
+        print(f"example 5.1  M={M:5d} L={L:5d}  alg 4.2 {row['alg4_2']['max_err_vs_f']:.3e}  "
+              f"alg 2.1 same beta {row['alg2_1_same_beta']['max_err_vs_f']:.3e}  "
+              f"alg 2.1 standard beta {row['alg2_1_standard_beta']['max_err_vs_f']:.3e}",
+              file=sys.stderr)
     Ms = EXAMPLE51_M_PAPER
     ins = []
     for M in Ms:   # FP32 inputs; the exact f and the oracle see the same rounded values
@@ -573,27 +608,59 @@ def oracle_leg(checks: list, name: str, nodes: int) -> dict:
     return cpu_baseline(name, nodes)
 
 
-def cpu_baseline(name: str, nodes: int):
-    """The oracle as it stands (numpy FP64), steps 1-3: full grid steps 1-2 plus step 3 on
-    a seeded node sample, the step-3 time scaled to the full node count."""
+def cpu_baseline(name: str, nodes: int, runs: int = 5, direct_nodes: int = 4000):
+    """The oracle as it stands (numpy FP64) on every host core this process may use:
+    steps 1-2 on the full grid with the BLAS/FFT threads of numpy, then step 3 over node
+    chunks in a thread pool (numpy releases the interpreter lock inside its array
+    operations), the median of `runs` runs; `nodes` caps the step-3 sample (its time is
+    scaled to the full node count).  The direct O(N M^d) sum, the target both algorithms
+    approximate, is timed on `direct_nodes` nodes and extrapolated to N."""
+    import statistics
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
     from threadpoolctl import threadpool_limits
 
     import oracle as O
     import workloads as W
     p = W.make_problem(name, precision="f32")
     n = min(nodes, p.N)
+    cores = len(os.sched_getaffinity(0))
     beta = O.default_beta(p.M, p.L, p.m)
-    with threadpool_limits(limits=1):
+    chunks = np.array_split(np.arange(n), 4 * cores)
+    t12, t3 = [], []
+    for _ in range(runs):
+        with threadpool_limits(limits=cores):
+            t0 = time.perf_counter()
+            theta = O.inverse_fft_step(O.deconvolve_pad(p.fhat, p.L, p.m, beta))
+            t1 = time.perf_counter()
+        with threadpool_limits(limits=1), ThreadPoolExecutor(cores) as ex:
+            t2 = time.perf_counter()
+            list(ex.map(lambda c: O.gather_shannon(theta, p.x[c], p.L, p.m, beta), chunks))
+            t3.append(time.perf_counter() - t2)
+        t12.append(t1 - t0)
+    t_full = statistics.median(t12) + statistics.median(t3) * (p.N / n)
+    nd = min(direct_nodes, p.N)
+    dchunks = np.array_split(np.arange(nd), cores)
+    with threadpool_limits(limits=1), ThreadPoolExecutor(cores) as ex:
         t0 = time.perf_counter()
-        theta = O.inverse_fft_step(O.deconvolve_pad(p.fhat, p.L, p.m, beta))
-        t1 = time.perf_counter()
-        O.gather_shannon(theta, p.x[:n], p.L, p.m, beta)
-        t2 = time.perf_counter()
-    t_full = (t1 - t0) + (t2 - t1) * (p.N / n)
-    return {"value": p.N / t_full, "unit": "node evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"numpy FP64 oracle, one thread: steps 1-2 on the full {p.L}^{p.d} grid "
-                      f"({t1 - t0:.2f} s) + step 3 on {n} of {p.N} nodes ({t2 - t1:.2f} s), "
-                      f"step-3 time scaled by {p.N / n:.1f}"}
+        list(ex.map(lambda c: O.direct_sum(p.fhat, p.x[c]), dchunks))
+        t_direct = (time.perf_counter() - t0) * (p.N / nd)
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": p.N / t_full, "unit": "node evals/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model, "runs": runs,
+            "sample": f"numpy FP64 oracle on {cores} host threads, median of {runs} runs: steps 1-2 "
+                      f"on the full {p.L}^{p.d} grid ({statistics.median(t12):.3f} s) + step 3 on "
+                      f"{n} of {p.N} nodes in {len(chunks)} chunks ({statistics.median(t3):.3f} s)"
+                      + (f", step-3 time scaled by {p.N / n:.1f}" if n < p.N else ""),
+            "direct_sum": {"value_extrapolated": p.N / t_direct, "unit": "node evals/s",
+                           "sample": f"direct O(N M^d) sum on {nd} nodes, {cores} threads, "
+                                     f"time extrapolated to {p.N} nodes ({t_direct:.1f} s)"}}
 
 
 def _csv_rows(directory: str, suffix: str):
@@ -621,29 +688,33 @@ def _counter_per_dispatch(directory: str, keep):
     return (sum(vals) / len(vals), len(vals)) if vals else (float("nan"), 0)
 
 
-def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir) -> str:
-    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the gather, each divided by the
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel: str = "gather",
+                      per_launch: int = 1) -> str:
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the gather (kernel "gather") or of the
+    FFT passes (kernel "fft": per_launch passes per transform, summed), each divided by the
     counter-to-bytes factor of a 1 GiB device copy (which reads and writes 1 GiB)."""
-    def gather(name):
-        return "k_gather<" in name
+    def pick(name):
+        return ("k_gather<" in name) if kernel == "gather" else ("k_fft_pass<" in name or "k_czt_pass<" in name)
 
     def copy(name):
         return True   # the calibration run launches nothing but the copies
 
-    fetch, nf = _counter_per_dispatch(fetch_dir, gather)
-    write, nw = _counter_per_dispatch(write_dir, gather)
+    fetch, nf = _counter_per_dispatch(fetch_dir, pick)
+    write, nw = _counter_per_dispatch(write_dir, pick)
     cf, ncf = _counter_per_dispatch(copy_fetch_dir, copy)
     cw, ncw = _counter_per_dispatch(copy_write_dir, copy)
     gib_kib = float(1 << 20)
     ff, fw = cf / gib_kib, cw / gib_kib
-    traffic = (fetch / ff + write / fw) * 1024.0
+    traffic = (fetch / ff + write / fw) * 1024.0 * per_launch
+    sources = GATHER_SOURCES if kernel == "gather" else FFT_SOURCES
     return "\n".join([
-        f"gather_fetch_kib_per_dispatch: {fetch:.1f}  (dispatches: {nf})",
-        f"gather_write_kib_per_dispatch: {write:.1f}  (dispatches: {nw})",
+        f"{kernel}_fetch_kib_per_dispatch: {fetch:.1f}  (dispatches: {nf})",
+        f"{kernel}_write_kib_per_dispatch: {write:.1f}  (dispatches: {nw})",
+        f"dispatches_per_launch: {per_launch}",
         f"copy_fetch_kib_per_GiB_copy: {cf:.1f}  (dispatches: {ncf}); factor {ff:.4f}",
         f"copy_write_kib_per_GiB_copy: {cw:.1f}  (dispatches: {ncw}); factor {fw:.4f}",
         f"traffic_bytes_per_launch: {traffic:.6e}",
-        f"source_sha256: {source_digest(GATHER_SOURCES)}",
+        f"source_sha256: {source_digest(sources)}",
     ])
 
 
@@ -667,7 +738,8 @@ def main():
         print(summarize_trace(args.summarize_trace))
         return
     if args.summarize_traffic:
-        print(summarize_traffic(*args.summarize_traffic))
+        print(summarize_traffic(*args.summarize_traffic, kernel=args.traffic_kernel,
+                                per_launch=args.traffic_passes))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -722,8 +794,9 @@ def main():
     ab = algorithmic_bytes(p.d, p.M, p.L, p.N, csize, rsize)
     flops = gather_flops_per_node(p.d, p.m) * p.N
     peak = FP64_PEAK_TFLOPS if prec == "f64" else FP32_PEAK_TFLOPS
+    published = 78.6 if prec == "f64" else FP32_PUBLISHED_TFLOPS
     gather_tflops = flops / (gms * 1e-3) / 1e12
-    fft_ms = max(ms - gms, 1e-9)
+    fft_ms = plan.fft_ms
     traffic = measured_traffic() if (args.workload == HEADLINE and prec == "f32c") else None
     rec = {
         "metric": METRIC,
@@ -748,10 +821,22 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_gather (step 3 short sums)",
                      "achieved": gather_tflops, "peak": peak, "unit": "TFLOP/s",
                      "frac": gather_tflops / peak, "traffic": traffic,
+                     "peak_basis": PEAK_BASIS, "peak_published": published,
+                     "frac_vs_published": gather_tflops / published,
                      "algorithmic_flops_per_launch": flops,
                      "per_node_flops": gather_flops_per_node(p.d, p.m),
                      "per_node_flops_contraction_only": mac_flops_per_node(p.d, p.m),
                      "frac_contraction_only": mac_flops_per_node(p.d, p.m) * p.N / (gms * 1e-3) / 1e12 / peak},
+        "roofline_fft": {"bound": "hbm", "kernel": "k_fft_pass (steps 1-2: deconvolution, zero-padding, "
+                                                  f"{p.d} pruned passes)",
+                         "achieved": ab["fft"] / (fft_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ab["fft"] / (fft_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "traffic": measured_fft_traffic(args.workload, prec),
+                         "algorithmic_bytes_per_launch": ab["fft"],
+                         "ms_per_launch": fft_ms,
+                         "note": "all passes of one transform between HIP events on the plan's stream "
+                                 "(bl_samples); algorithmic bytes: every pruned pass reads and writes "
+                                 "its lines once in the data type"},
         "hbm": {"algorithmic_bytes": ab, "deconv_fft_GBs": ab["fft"] / (fft_ms * 1e-3) / 1e9,
                 "gather_GBs": ab["gather"] / (gms * 1e-3) / 1e9, "peak_GBs": HBM_PEAK_GBS,
                 "copy_GBs": None if args.headline_only else copy_bandwidth(torch),

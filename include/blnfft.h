@@ -11,8 +11,8 @@
  * ------------------------------
  *  - Pointers named *_dev are device pointers (hipMalloc'd or equivalent, on the device the
  *    plan was created on).  The caller owns them; the library never frees them.
- *  - Precision: BL_F64 uses double / interleaved double2 complex.  BL_F32 and BL_F32C use
- *    float / interleaved float2 complex for every input and output.
+ *  - Precision: BL_F64 uses double / interleaved double2 complex.  BL_F32, BL_F32C and
+ *    BL_F32D use float / interleaved float2 complex for every input and output.
  *  - fhat is an M^d complex array, row-major (last dimension fastest); array index i_t
  *    holds frequency k_t = i_t - M/2.
  *  - Nodes x are an N x d real array, row-major (x[j*d + t]), each coordinate in [-1/2, 1/2).
@@ -58,12 +58,18 @@ typedef enum {
 
 typedef enum {
     BL_F64 = 0,           /* everything in double                                       */
-    BL_F32 = 1,           /* float data and arithmetic, FP64-derived twiddles/factors   */
-    BL_F32C = 2           /* float inputs, outputs and grid of samples; the FFT passes
+    BL_F32 = 1,           /* float data and arithmetic; twiddles and deconvolution
+                             factors formed in FP64 and rounded to float; plain sums    */
+    BL_F32C = 2,          /* float data, arithmetic and intermediates; FP64 kept only for
+                             the FFT twiddles (and chirps) and the deconvolution factors,
+                             whose products are formed in double and rounded once; short
+                             sums with float weights and float inner sums, the outermost
+                             sum compensated by error-free two-sums                     */
+    BL_F32D = 3           /* float inputs, outputs and grid of samples; the FFT passes
                              compute in double with double intermediates (one rounding,
-                             at the store of the grid); short sums with float weights,
-                             inner sums in float and the outermost sum accumulated in
-                             double (float products are exact in double)              */
+                             at the store of the grid); short sums as BL_F32C but with
+                             the outermost sum accumulated in double (float products
+                             are exact in double)                                       */
 } bl_precision;
 
 typedef struct bl_plan_s* bl_plan;
@@ -77,6 +83,14 @@ typedef struct {
     int64_t chunk_cap;        /* max nodes per work item                                   */
     int64_t workspace_bytes;  /* device memory owned by the plan                           */
     double beta;              /* window shape parameter in use                             */
+    double weight_fit_err;    /* largest deviation of the fitted weight polynomials from
+                                 the exact weights psi(x - l/L), relative to the largest
+                                 weight (0 when FP64 plans evaluate them exactly)          */
+    int64_t fft_lines[2][3];  /* lines per workgroup of the forward [0] and adjoint [1]
+                                 transform pass over each axis (0: the built-in rule)      */
+    int64_t tuned[2];         /* how the FFT lines [0] and the tile edge and chunk
+                                 capacity [1] were chosen: 0 built-in rule or environment
+                                 override, 1 timed by this plan, 2 from the tuning cache   */
 } bl_stats;
 
 /* Create a plan.  Algorithm 4.2 step 0a (psihat(k), k in I_M; eq. (4.9)) or Algorithm 2.1
@@ -84,8 +98,10 @@ typedef struct {
  *   d      : 1, 2 or 3.
  *   M      : bandwidth per dimension, even, >= 2 (I_M, Section 1).
  *   L      : oversampled grid per dimension, even, L >= M (Algorithm 4.2, L = M(1+lambda)),
- *            L <= 8192.  bl_forward and bl_adjoint need a power of two L >= 16 (their FFT);
- *            any even L gives a plan whose short sums (bl_interpolate) run.
+ *            L <= 32768 for d = 1 and L <= 8192 for d = 2, 3 (BL_EUNSUPPORTED above).
+ *            Any such L runs the short sums; bl_forward and bl_adjoint run every L of
+ *            d = 1 and, for d >= 2, L with L + M - 1 within the in-LDS chirp-z transform
+ *            or L a power of two (see bl_forward).
  *   m      : truncation, 1 <= m and 2m < L; this build's kernels take 2 <= m <= 8
  *            (BL_EUNSUPPORTED otherwise).
  *   win    : window: BL_WIN_SINH (eq. (3.4)) or BL_WIN_CKB (continuous Kaiser-Bessel,
@@ -93,9 +109,12 @@ typedef struct {
  *            with BL_WIN_CKB an FP64 plan needs its fit within 1e-13 (BL_EUNSUPPORTED
  *            otherwise), and FP64 bl_grad_x differentiates the fitted polynomials.
  *   beta   : window parameter; beta <= 0 picks the default: pi*m*(L-M)/L for BL_SHANNON,
- *            2*pi*m*(1 - M/(2L)) for BL_NFFT.
+ *            2*pi*m*(1 - M/(2L)) for BL_NFFT.  Float plans (BL_F32, BL_F32C) evaluate the
+ *            weights by degree-11 polynomials and refuse (BL_EUNSUPPORTED) a beta at which
+ *            their fit error exceeds 1e-7 (only far above the defaults, e.g. beta > ~25 at
+ *            m = 2); bl_plan_stats reports the fit error.
  *   method : BL_SHANNON or BL_NFFT.
- *   prec   : BL_F64, BL_F32 or BL_F32C.
+ *   prec   : BL_F64, BL_F32, BL_F32C or BL_F32D.
  *   stream : hipStream_t (as void*) for every later call.
  * Synchronous.  Allocates the plan's device workspace (grid of L^d complex samples,
  * FFT intermediates, tables).  On error *out is set to NULL and nothing is allocated. */
@@ -128,9 +147,16 @@ bl_status bl_precompute_weights(bl_plan plan, int enable);
  *   step 3: f_j = sum_{l in J_{L,m}(x_j)} theta_l psi(x_j - l/L)           (4.8),
  * with theta_l = 0 for l outside I_L (zero-extended sum; BL_NFFT wraps periodically).
  *   fhat_dev : M^d complex (input).   f_dev : N complex (output, overwritten).
- * Asynchronous.  Keeps theta for bl_grad_x / bl_get_theta.  BL_EUNSUPPORTED unless L is a
- * power of two >= 16. */
+ * Asynchronous.  Keeps theta for bl_grad_x / bl_get_theta.  Step 2 runs power-of-two
+ * L <= 8192 as radix-4/16 passes and any other L as chirp-z (Bluestein) passes with a cyclic
+ * convolution of power-of-two size P >= L + M - 1; BL_EUNSUPPORTED when d >= 2 and P exceeds
+ * the in-LDS transform (8192 points for BL_F64 and BL_F32D, 16384 for BL_F32 and BL_F32C). */
 bl_status bl_forward(bl_plan plan, const void* fhat_dev, void* f_dev);
+
+/* Steps 1-2 alone (Algorithm 4.2 or 2.1): the samples theta_l, l in I_L, of (4.7) from
+ * fhat_dev (M^d complex), kept in the plan for bl_get_theta and bl_grad_x.  Needs no bound
+ * nodes.  The same L restrictions as bl_forward.  Asynchronous. */
+bl_status bl_samples(bl_plan plan, const void* fhat_dev);
 
 /* Regularized Shannon sampling formula (3.5) truncated to I_L: evaluate step 3 alone on
  * given samples theta_dev (L^d complex, centred order) at the bound nodes (BL_NFFT: the
@@ -145,11 +171,20 @@ bl_status bl_get_theta(bl_plan plan, void* theta_dev);
 /* Adjoint of the factorisation (4.11): fhat_out = D_psihat^H F^H Psi^T g  (BL_SHANNON), or
  * D^H F^H B^T g (BL_NFFT).  D is real; F^H uses e^{-2 pi i k l / L}.
  *   g_dev : N complex (input).   fhat_dev : M^d complex (output, overwritten).
- * Asynchronous.  BL_EUNSUPPORTED unless L is a power of two >= 16. */
+ * Psi^T g is formed without atomic additions in device memory: each work chunk of nodes
+ * writes its tile-plus-halo box, and the boxes are summed per grid point in a fixed order,
+ * so for one node binding repeated calls give bitwise equal results (the LDS-atomic
+ * spreading kernel, which only the BL_SPREAD_ATOMIC override or a tile edge set by BL_TILE
+ * beyond the other kernels' boxes selects, sums within a work chunk in no fixed order).  The first call (and
+ * a call after a binding with more work chunks) allocates the spreading grid and boxes.
+ * Asynchronous.  The same L restrictions as bl_forward. */
 bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev);
 
 /* Gradient with respect to the nodes: gx[j*d + t] = Re( conj(g_j) * d f_j / d x_jt ),
- * f from the last bl_forward (BL_SHANNON only).  With g = 2(f - y) this is the gradient
+ * f from the last bl_forward (BL_SHANNON only).  f_j is the short sum (4.8) over the
+ * samples theta of step 2 (the factorisation (4.11) with Psi's entries psi(x_j - l/L)),
+ * so d f_j / d x_jt = L sum_l theta_l psi'(L x_jt - l_t) prod_{s != t} psi(L x_js - l_s)
+ * in grid units, with psi' of the regularized sinc (4.2).  With g = 2(f - y) this is the gradient
  * of sum_j |f_j - y_j|^2.   g_dev : N complex.  gx_dev : N x d real (output).
  * BL_ESTATE if no forward has run since the last bl_set_nodes.  FP64 plans with
  * BL_WIN_CKB take the weight derivatives from the fitted weight polynomials; their
@@ -157,7 +192,10 @@ bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev);
  * BL_EUNSUPPORTED is returned if it exceeds 5e-12.  Asynchronous. */
 bl_status bl_grad_x(bl_plan plan, const void* g_dev, void* gx_dev);
 
-/* Plan statistics.  Synchronous with respect to host state only. */
+/* Plan statistics: the bound node count and how many of the nodes lie outside the
+ * truncated domain [-1/2 + m/L, 1/2 - m/L)^d of Algorithm 4.2 (Section 4, where the short
+ * sums (4.8) reach grid points outside I_L), the work decomposition of step 3, the
+ * workspace and the window's beta (3.4).  Synchronous with respect to host state only. */
 bl_status bl_plan_stats(bl_plan plan, bl_stats* out);
 
 /* Destroy a plan (synchronizes its stream, frees its workspace).  NULL is accepted. */
@@ -170,7 +208,7 @@ bl_status bl_plan_destroy(bl_plan plan);
 bl_status bl_window_transform(bl_window win, bl_method method, int64_t M, int64_t L, int m,
                               double beta, int64_t n, const double* v, double* out);
 
-/* Batched d = 1 transforms (Algorithm 4.2 with the sinh-type window of (2.5) and the
+/* Batched d = 1 transforms (Algorithm 4.2 with the sinh-type window of (3.4) and the
  * default shape parameter beta = pi m (L - M) / L) of `count` independent instances with
  * their own (M_i, L_i, m_i, N_i), executed as one graph launch: steps 1-2 of every
  * instance in one kernel (one workgroup per instance, any even L_i via the chirp-z form of

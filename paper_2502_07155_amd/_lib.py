@@ -14,10 +14,11 @@ LIB_PATH = os.path.join(HERE, "libblnfft.so")
 BL_OK, BL_EINVAL, BL_EDOMAIN, BL_ENOMEM, BL_EDEVICE, BL_ESTATE, BL_EUNSUPPORTED = range(7)
 WINDOWS = {"sinh": 0, "ckb": 1}
 METHODS = {"shannon": 0, "nfft": 1}
-PRECISIONS = {"f64": 0, "f32": 1, "f32c": 2}
+PRECISIONS = {"f64": 0, "f32": 1, "f32c": 2, "f32d": 3}
 
 EXPORTS = [
-    "bl_plan_create", "bl_set_nodes", "bl_precompute_weights", "bl_forward", "bl_interpolate",
+    "bl_plan_create", "bl_set_nodes", "bl_precompute_weights", "bl_forward", "bl_samples",
+    "bl_interpolate",
     "bl_get_theta",
     "bl_adjoint", "bl_grad_x", "bl_plan_stats", "bl_plan_destroy", "bl_window_transform",
     "bl_batch_create", "bl_batch_set_nodes", "bl_batch_forward", "bl_batch_destroy",
@@ -40,6 +41,9 @@ class Stats(ctypes.Structure):
         ("chunk_cap", ctypes.c_int64),
         ("workspace_bytes", ctypes.c_int64),
         ("beta", ctypes.c_double),
+        ("weight_fit_err", ctypes.c_double),
+        ("fft_lines", ctypes.c_int64 * 6),
+        ("tuned", ctypes.c_int64 * 2),
     ]
 
 
@@ -62,6 +66,7 @@ def load() -> ctypes.CDLL:
         "bl_set_nodes": [vp, i64, vp],
         "bl_precompute_weights": [vp, i32],
         "bl_forward": [vp, vp, vp],
+        "bl_samples": [vp, vp],
         "bl_interpolate": [vp, vp, vp],
         "bl_get_theta": [vp, vp],
         "bl_adjoint": [vp, vp, vp],

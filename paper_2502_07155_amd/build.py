@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libblnfft.so")
 
-SOURCES = ["api.cpp", "host_tables.cpp", "batch.hip", "fft.hip", "gather.hip", "spread.hip"]
+SOURCES = ["api.cpp", "autotune.cpp", "host_tables.cpp", "batch.hip", "fft.hip", "czt.hip", "gather.hip", "spread.hip"]
 ARCH = "gfx950"
 
 

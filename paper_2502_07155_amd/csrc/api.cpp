@@ -1,5 +1,7 @@
 // C ABI of the blnfft library: validation, plan lifecycle and call dispatch.
+#include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -65,11 +67,24 @@ void free_nodes(Plan& p) {
     p.chunk_alloc = 0;
 }
 
+// Destroy one cached forward graph.  A replay launched before may still be running on the
+// plan's stream, so the stream is synchronized before its executable graph is destroyed.
+void drop_one_graph(Plan& p, Plan::FwdGraph& g) {
+    if (!g.exec) return;
+    (void)hipStreamSynchronize(p.stream);
+    hipGraphExecDestroy(g.exec);
+    g = Plan::FwdGraph{};
+}
+
 void drop_graph(Plan& p) {
-    if (p.fwd_exec) hipGraphExecDestroy(p.fwd_exec);
-    p.fwd_exec = nullptr;
-    p.fwd_fhat = nullptr;
-    p.fwd_f = nullptr;
+    bool any = false;
+    for (auto& g : p.graphs) any = any || g.exec != nullptr;
+    if (!any) return;
+    (void)hipStreamSynchronize(p.stream);
+    for (auto& g : p.graphs) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        g = Plan::FwdGraph{};
+    }
 }
 
 void free_plan(Plan& p) {
@@ -87,6 +102,9 @@ void free_plan(Plan& p) {
     hipFree(p.d_bufB);
     hipFree(p.d_grid);
     hipFree(p.d_sgrid);
+    hipFree(p.d_boxes);
+    p.d_boxes = nullptr;
+    p.boxes_cap = 0;
     hipFree(p.d_tile_count);
     hipFree(p.d_tile_offset);
     hipFree(p.d_tile_cursor);
@@ -95,39 +113,161 @@ void free_plan(Plan& p) {
     hipFree(p.d_wpre);
     p.d_wpre = nullptr;
     p.use_wpre = false;
+    for (void** t : {&p.czt.d_roots64, &p.czt.d_roots32, &p.czt.d_H64, &p.czt.d_H32, &p.czt.d_band64,
+                     &p.czt.d_band32, &p.czt.d_grid64, &p.czt.d_grid32, &p.czt.d_scr}) {
+        hipFree(*t);
+        *t = nullptr;
+    }
 }
 
-// Tile edge per dimension for the short-sum kernels: the default edge, shrunk until the
-// staged tile plus halo (stored twice for float tiles with d >= 2) fits the LDS budget.
-// The d = 3 budget keeps at least three workgroups per CU (measured: occupancy outweighs
-// the larger halo overhead there).
-void choose_tiles(Plan& p) {
-    const int d = p.d;
-    const size_t budget = (d == 3 ? 44 : 64) * 1024;
-    auto box = [&](int t) {
-        size_t e = 1;
-        for (int k = 0; k < d; ++k) e *= size_t(t + 2 * p.m - 1);
-        return e;
-    };
-    p.dual_tiles = dual_tiles_for(d, p.m, p.prec != BL_F64);
+// LDS budget of one staged tile plus halo (stored twice for float tiles with d >= 2).  The
+// d = 3 budget keeps at least three workgroups per CU (measured: occupancy outweighs the
+// larger halo overhead there).
+bool tile_fits(const Plan& p, int T) {
+    size_t e = 1;
+    for (int k = 0; k < p.d; ++k) e *= size_t(T + 2 * p.m - 1);
     const size_t c = p.cplx_size() * (p.dual_tiles ? 2 : 1);
-    int T;
-    if (d == 1) T = 512;
-    else if (d == 2) T = 16;
-    else T = 8;
+    return e * c <= size_t(p.d == 3 ? 44 : 64) * 1024;
+}
+
+// Default tile edge of the short-sum kernels, shrunk until the tile fits its LDS budget.
+int default_tile(const Plan& p) {
+    int T = p.d == 1 ? 512 : p.d == 2 ? 16 : 8;
     if (const char* e = std::getenv("BL_TILE")) {   // tuning override
         const int v = std::atoi(e);
         if (v >= 1 && v <= 4096) T = v;
     }
-    while (T > 1 && box(T) * c > budget) --T;
-    if (T > p.L) T = int(p.L);
+    while (T > 1 && !tile_fits(p, T)) --T;
+    return int(std::min<int64_t>(T, p.L));
+}
+
+// Candidates of the autotuner: (tile edge, chunk capacity) pairs whose tile fits its LDS
+// budget and whose box (tile + 2m - 1) keeps the adjoint's deterministic spreading kernels:
+// the output-stationary one for d = 1 (<= 1024 points), the row kernels for d = 2 and 3
+// (edges <= 32 and <= 16).
+std::vector<std::pair<int, int>> tile_candidates(const Plan& p) {
+    std::vector<int> Ts;
+    if (p.d == 1) Ts = {256, 512, 1024, 2048};
+    else if (p.d == 2) Ts = {12, 14, 16, 20, 24};
+    else Ts = {5, 6, 7, 8};
+    std::vector<int> caps = p.d == 1 ? std::vector<int>{1024} : std::vector<int>{512, 1024};
+    std::vector<std::pair<int, int>> out;
+    for (int T : Ts) {
+        if (T > p.L || !tile_fits(p, T)) continue;
+        if (p.d == 1 && T + 2 * p.m - 1 > 1024) continue;   // output-stationary spreading
+        if (p.d == 2 && T + 2 * p.m - 1 > 32) continue;
+        if (p.d == 3 && p.m <= 7 && T + 2 * p.m - 1 > 16) continue;
+        for (int c : caps) out.push_back({T, c});
+    }
+    return out;
+}
+
+int64_t tiles_for(const Plan& p, int T) {
+    int64_t n = 1;
+    for (int t = 0; t < p.d; ++t) n *= (p.L + T - 1) / T;
+    return n;
+}
+
+// Sets the tile edge and the chunk capacity, growing the per-tile arrays when needed.
+bl_status apply_tiles(Plan& p, int T, int cap) {
     p.ntiles = 1;
     for (int t = 0; t < 3; ++t) {
-        p.tile[t] = t < d ? T : 1;
-        p.tiles_per_dim[t] = t < d ? int((p.L + T - 1) / T) : 1;
+        p.tile[t] = t < p.d ? T : 1;
+        p.tiles_per_dim[t] = t < p.d ? int((p.L + T - 1) / T) : 1;
         p.ntiles *= p.tiles_per_dim[t];
     }
-    p.chunk_cap = 1024;
+    p.chunk_cap = cap;
+    if (p.ntiles <= p.tile_alloc) return BL_OK;
+    BL_HIP(hipStreamSynchronize(p.stream));
+    for (int32_t** a : {&p.d_tile_count, &p.d_tile_offset, &p.d_tile_cursor, &p.d_chunk_offset}) {
+        hipFree(*a);
+        *a = nullptr;
+    }
+    p.workspace_bytes -= size_t(p.tile_alloc) * 4 * sizeof(int32_t);
+    p.tile_alloc = 0;
+    size_t extra = 0;
+    for (int32_t** a : {&p.d_tile_count, &p.d_tile_offset, &p.d_tile_cursor, &p.d_chunk_offset})
+        BL_TRY(dev_alloc(a, sizeof(int32_t) * size_t(p.ntiles), &extra));
+    p.tile_alloc = p.ntiles;
+    p.workspace_bytes += extra;
+    return BL_OK;
+}
+
+// Average time (ms) of the short-sum kernel on the bound nodes (zero samples).
+double time_gather(Plan& p, void* f, hipEvent_t e0, hipEvent_t e1) {
+    if (launch_gather(p, p.d_grid, f) != BL_OK) return -1.0;
+    if (hipEventRecord(e0, p.stream) != hipSuccess) return -1.0;
+    constexpr int reps = 3;
+    for (int r = 0; r < reps; ++r)
+        if (launch_gather(p, p.d_grid, f) != BL_OK) return -1.0;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, p.stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        return -1.0;
+    return double(ms) / reps;
+}
+
+// Node binning with the autotuned tile edge and chunk capacity: the nodes are binned with
+// the default tiles first, which classifies them (nodes per grid point, fullest tile
+// against the mean); a cached choice for that class is applied, or every candidate is
+// timed and the fastest kept and cached.  A later binning of as many nodes keeps the
+// plan's choice.
+bl_status bin_tuned(Plan& p, const void* x, int64_t N) {
+    if (!tile_tuning_wanted(p, N) || (p.tuned_N == N && p.tune_tile_source != 0))
+        return launch_binning(p, x, N);
+    BL_TRY(apply_tiles(p, default_tile(p), 1024));
+    BL_TRY(launch_binning(p, x, N));
+    std::vector<int32_t> cnt(size_t(p.ntiles));
+    BL_HIP(hipMemcpy(cnt.data(), p.d_tile_count, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost));
+    const double mean = double(N) / double(p.ntiles);
+    const double fullest = double(*std::max_element(cnt.begin(), cnt.end()));
+    const int density = int(std::lround(2.0 * std::log2(double(N) / double(p.grid_elems()))));
+    const int cluster = int(std::lround(std::log2(std::max(1.0, fullest / mean))));
+    int T = p.tile[0], cap = p.chunk_cap;
+    const int T0 = T, cap0 = cap;
+    if (tile_cache_lookup(p, density, cluster, &T, &cap)) {
+        p.tune_tile_source = 2;
+    } else {
+        const auto cands = tile_candidates(p);
+        if (cands.empty()) return BL_OK;
+        void* f = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        BL_TRY(dev_alloc(reinterpret_cast<char**>(&f), size_t(N) * p.cplx_size(), &p.workspace_bytes));
+        p.workspace_bytes -= size_t(N) * p.cplx_size();
+        bl_status st = BL_OK;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+            hipMemsetAsync(p.d_grid, 0, size_t(p.grid_elems()) * p.cplx_size(), p.stream) != hipSuccess) {
+            st = fail(BL_EDEVICE, "autotuner: event or memset failed");
+        }
+        double best_ms = -1.0;
+        for (size_t i = 0; st == BL_OK && i < cands.size(); ++i) {
+            st = apply_tiles(p, cands[i].first, cands[i].second);
+            if (st == BL_OK) st = launch_binning(p, x, N);
+            if (st != BL_OK) break;
+            const double ms = time_gather(p, f, e0, e1);
+            if (ms > 0.0 && (best_ms < 0.0 || ms < best_ms)) {
+                best_ms = ms;
+                T = cands[i].first;
+                cap = cands[i].second;
+            }
+        }
+        (void)hipStreamSynchronize(p.stream);
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        hipFree(f);
+        BL_TRY(st);
+        if (best_ms < 0.0) {
+            T = T0;
+            cap = cap0;
+        } else {
+            tile_cache_store(p, density, cluster, T, cap);
+            p.tune_tile_source = 1;
+        }
+    }
+    p.tuned_N = N;
+    if (T == p.tile[0] && cap == p.chunk_cap) return BL_OK;
+    BL_TRY(apply_tiles(p, T, cap));
+    return launch_binning(p, x, N);
 }
 
 // Steps 1-3 as kernel launches on p.stream.
@@ -136,9 +276,18 @@ bl_status forward_launches(Plan& p, const void* fhat, void* f) {
     return launch_gather(p, p.d_grid, f);
 }
 
-// Capture the forward launches into a graph on the private capture stream.
-bl_status capture_forward(Plan& p, const void* fhat, void* f) {
-    drop_graph(p);
+// Capture the forward launches into a graph on the private capture stream, into a free
+// cache slot or the least recently used one.
+bl_status capture_forward(Plan& p, const void* fhat, void* f, Plan::FwdGraph** out) {
+    Plan::FwdGraph* slot = &p.graphs[0];
+    for (auto& g : p.graphs) {
+        if (!g.exec) {
+            slot = &g;
+            break;
+        }
+        if (g.used < slot->used) slot = &g;
+    }
+    drop_one_graph(p, *slot);
     if (!p.capture_stream) BL_HIP(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
     hipStream_t user = p.stream;
     p.stream = p.capture_stream;
@@ -159,9 +308,10 @@ bl_status capture_forward(Plan& p, const void* fhat, void* f) {
     e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e != hipSuccess) return fail(BL_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-    p.fwd_exec = ge;
-    p.fwd_fhat = fhat;
-    p.fwd_f = f;
+    slot->exec = ge;
+    slot->fhat = fhat;
+    slot->f = f;
+    *out = slot;
     return BL_OK;
 }
 
@@ -218,17 +368,26 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     if (m < 1 || 2 * int64_t(m) >= L) return fail(BL_EINVAL, "need 1 <= m and 2m < L");
     if (win != BL_WIN_SINH && win != BL_WIN_CKB) return fail(BL_EINVAL, "unknown window");
     if (method != BL_SHANNON && method != BL_NFFT) return fail(BL_EINVAL, "unknown method");
-    if (prec != BL_F64 && prec != BL_F32 && prec != BL_F32C) return fail(BL_EINVAL, "unknown precision");
+    if (prec != BL_F64 && prec != BL_F32 && prec != BL_F32C && prec != BL_F32D)
+        return fail(BL_EINVAL, "unknown precision");
     if (std::isnan(beta) || std::isinf(beta)) return fail(BL_EINVAL, "beta not finite");
     if (m < kMinM || m > kMaxM)
         return fail(BL_EUNSUPPORTED, "compiled short-sum kernels cover 2 <= m <= 8");
-    // The per-plan FFT needs a power of two L >= 16; other even L give plans whose short sums
-    // (bl_interpolate) run, while bl_forward and bl_adjoint report BL_EUNSUPPORTED.
+    // Steps 1-2 and the adjoint: power-of-two L in [16, 8192] run the Stockham passes; any
+    // other even L the chirp-z passes with a cyclic convolution of power-of-two size
+    // P >= L + M - 1, held in LDS when P fits (8192 points in double arithmetic, 16384 in
+    // float), else, for d = 1 only, split into up to eight LDS pieces.  A d >= 2 plan whose
+    // P exceeds the LDS size still runs the short sums (bl_interpolate) alone.
+    const int64_t Lmax = d == 1 ? 32768 : 8192;
+    if (L > Lmax) return fail(BL_EUNSUPPORTED, "L above " + std::to_string(Lmax) + " for d = " + std::to_string(d));
     FftFactors fac16, fac4;
-    const bool fft_ok = L <= (1 << 30) && factor_length(int(L), 16, &fac16) && factor_length(int(L), 4, &fac4);
-    // one line of L complex values per LDS pass with <= 512 threads of 16 values each
-    const int64_t Lmax = 8192;
-    if (L > Lmax) return fail(BL_EUNSUPPORTED, "L above the LDS FFT limit for this precision");
+    const bool stockham_ok = L <= 8192 && factor_length(int(L), 16, &fac16) && factor_length(int(L), 4, &fac4);
+    const bool f64 = prec == BL_F64 || prec == BL_F32D;
+    const int64_t lds_points = f64 ? kCztLdsPoints<double>() : kCztLdsPoints<float>();
+    int64_t czP = 4;
+    while (czP < L + M - 1) czP *= 2;
+    const bool czt_split = czP > lds_points;
+    const bool fft_ok = stockham_ok || !czt_split || (d == 1 && czP <= 8 * lds_points);
     const int64_t grid = ipow(L, d);
     if (grid > (int64_t(1) << 31)) return fail(BL_EUNSUPPORTED, "grid L^d too large");
 
@@ -262,19 +421,19 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
         fac_h[i] = 1.0 / (double(L) * hv);
     }
     std::vector<double> tw0;
-    twiddles(L, &tw0);
+    if (stockham_ok) twiddles(L, &tw0);
     std::vector<double> tw[2];
     std::vector<float> tw32[2];
     const FftFactors* facs[2] = {&fac16, &fac4};
     FftStages* sts[2] = {&p.st16, &p.st4};
     for (int v = 0; v < 2; ++v) {
-        if (fft_ok) stage_twiddles(*facs[v], tw0, &tw[v], sts[v]->tw_off);
+        if (stockham_ok) stage_twiddles(*facs[v], tw0, &tw[v], sts[v]->tw_off);
         if (tw[v].empty()) tw[v].assign(2, 0.0);
         sts[v]->tw_len = int(tw[v].size() / 2);
         sts[v]->nmain = 0;
         sts[v]->rlast = 1;
         const int E = v == 0 ? 16 : 4;
-        for (int s = 0; fft_ok && s < facs[v]->nstages; ++s) {
+        for (int s = 0; stockham_ok && s < facs[v]->nstages; ++s) {
             if (facs[v]->radix[s] == E) ++sts[v]->nmain;
             else sts[v]->rlast = facs[v]->radix[s];
         }
@@ -285,6 +444,10 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     if (prec != BL_F64) {
         std::vector<double> pc;
         p.poly_err = fit_weight_polys(win, method, m, p.beta, kPolyCoef, &pc);
+        if (!(p.poly_err <= kPolyFitTol))
+            return cleanup(fail(BL_EUNSUPPORTED, "float weight polynomials fit this window only to " +
+                                                     std::to_string(p.poly_err) +
+                                                     " (above 1e-7; beta too large for float plans)"));
         p.poly.assign(pc.begin(), pc.end());
     } else {
         p.poly64_err = fit_weight_polys(win, method, m, p.beta, kPolyCoef64, &p.poly64);
@@ -314,17 +477,61 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
         if ((s = dev_alloc(&sts[v]->d_tw32, sizeof(float) * tw[v].size(), &total)) != BL_OK) return cleanup(s);
     }
     if ((s = dev_alloc(&p.d_grid, size_t(grid) * c, &total)) != BL_OK) return cleanup(s);
-    // F32C keeps the FFT pass intermediates in double.
-    const size_t ci = (prec == BL_F32) ? c : 16;
+    // F32D keeps the FFT pass intermediates in double.
+    const size_t ci = p.fft64() ? 16 : c;
     if ((s = dev_alloc(&p.d_bufA, size_t(A) * ci, &total)) != BL_OK) return cleanup(s);
     if ((s = dev_alloc(&p.d_bufB, size_t(B) * ci, &total)) != BL_OK) return cleanup(s);
-    choose_tiles(p);
-    if ((s = dev_alloc(&p.d_tile_count, sizeof(int32_t) * p.ntiles, &total)) != BL_OK) return cleanup(s);
-    if ((s = dev_alloc(&p.d_tile_offset, sizeof(int32_t) * p.ntiles, &total)) != BL_OK) return cleanup(s);
-    if ((s = dev_alloc(&p.d_tile_cursor, sizeof(int32_t) * p.ntiles, &total)) != BL_OK) return cleanup(s);
-    if ((s = dev_alloc(&p.d_chunk_offset, sizeof(int32_t) * p.ntiles, &total)) != BL_OK) return cleanup(s);
+    if (!stockham_ok && fft_ok) {
+        // chirp-z tables, FP64 (with float copies): u^{k^2} times the factor on I_M,
+        // u^{l^2} on I_L, H = DFT_P(h) / P and the P-th roots, u = e^{i pi / L}
+        CztTables& z = p.czt;
+        z.on = true;
+        z.P = czP;
+        z.split = czt_split;
+        z.R = czt_split ? int(czP / lds_points) : 1;
+        std::vector<double> tw2L, rootsP;
+        twiddles(2 * L, &tw2L);
+        twiddles(czP, &rootsP);
+        std::vector<double> band(2 * M), gridc(2 * L), Hd(2 * czP);
+        for (int64_t i = 0; i < M; ++i) {
+            const int64_t k = i - M / 2;
+            const std::complex<double> v = chirp(k * k, L, tw2L) * fac_h[i];
+            band[2 * i] = v.real();
+            band[2 * i + 1] = v.imag();
+        }
+        for (int64_t i = 0; i < L; ++i) {
+            const int64_t l = i - L / 2;
+            const std::complex<double> v = chirp(l * l, L, tw2L);
+            gridc[2 * i] = v.real();
+            gridc[2 * i + 1] = v.imag();
+        }
+        const std::vector<std::complex<double>> H = chirp_spectrum(L, M, czP);
+        for (int64_t q = 0; q < czP; ++q) {
+            Hd[2 * q] = H[q].real();
+            Hd[2 * q + 1] = H[q].imag();
+        }
+        struct Tab {
+            const std::vector<double>* v;
+            void** d64;
+            void** d32;
+        } tabs[4] = {{&band, &z.d_band64, &z.d_band32}, {&gridc, &z.d_grid64, &z.d_grid32},
+                     {&Hd, &z.d_H64, &z.d_H32}, {&rootsP, &z.d_roots64, &z.d_roots32}};
+        for (const Tab& tb : tabs) {
+            const size_t n = tb.v->size();
+            if ((s = dev_alloc(reinterpret_cast<char**>(tb.d64), sizeof(double) * n, &total)) != BL_OK) return cleanup(s);
+            if ((s = dev_alloc(reinterpret_cast<char**>(tb.d32), sizeof(float) * n, &total)) != BL_OK) return cleanup(s);
+            std::vector<float> f32(tb.v->begin(), tb.v->end());
+            if (hipMemcpy(*tb.d64, tb.v->data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(*tb.d32, f32.data(), sizeof(float) * n, hipMemcpyHostToDevice) != hipSuccess)
+                return cleanup(fail(BL_EDEVICE, "chirp-z table upload failed"));
+        }
+        if (czt_split && (s = dev_alloc(reinterpret_cast<char**>(&z.d_scr), size_t(czP) * ci, &total)) != BL_OK)
+            return cleanup(s);
+    }
+    p.dual_tiles = dual_tiles_for(d, p.m, p.prec != BL_F64);
+    if ((s = apply_tiles(p, default_tile(p), 1024)) != BL_OK) return cleanup(s);
     if ((s = dev_alloc(&p.d_flags, sizeof(unsigned long long) * 4, &total)) != BL_OK) return cleanup(s);
-    p.workspace_bytes = total;
+    p.workspace_bytes += total;
 
     hipError_t e = hipMemcpyAsync(p.d_deconv, fac_h.data(), sizeof(double) * M, hipMemcpyHostToDevice, p.stream);
     for (int v = 0; v < 2 && e == hipSuccess; ++v) {
@@ -334,6 +541,7 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
     }
     if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
     if (e != hipSuccess) return cleanup(fail(BL_EDEVICE, std::string("table upload: ") + hipGetErrorString(e)));
+    if ((s = autotune_fft(p)) != BL_OK) return cleanup(s);
     *out = h;
     return BL_OK;
 }
@@ -362,7 +570,14 @@ bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev) {
         p.d_wpre = nullptr;
     }
     p.use_wpre = false;
-    const int64_t chunk_bound = N / p.chunk_cap + p.ntiles + 1;
+    // work chunks: at most N / cap + ntiles + 1 for the current tiles and every candidate
+    // of the autotuner
+    int64_t chunk_bound = N / p.chunk_cap + p.ntiles + 1;
+    if (tile_tuning_wanted(p, N)) {
+        chunk_bound = std::max<int64_t>(chunk_bound, N / 1024 + tiles_for(p, default_tile(p)) + 1);
+        for (const auto& c : tile_candidates(p))
+            chunk_bound = std::max<int64_t>(chunk_bound, N / c.second + tiles_for(p, c.first) + 1);
+    }
     if (N > p.N_cap || chunk_bound > p.chunk_alloc) {
         BL_HIP(hipStreamSynchronize(p.stream));
         free_nodes(p);
@@ -372,12 +587,12 @@ bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev) {
         if ((s = dev_alloc(&p.d_xs, size_t(ncap) * p.d * p.real_size(), &extra)) != BL_OK) return s;
         if ((s = dev_alloc(&p.d_perm, sizeof(int32_t) * ncap, &extra)) != BL_OK) return s;
         if ((s = dev_alloc(&p.d_node_tile, sizeof(int32_t) * ncap, &extra)) != BL_OK) return s;
-        const int64_t cb = ncap / p.chunk_cap + p.ntiles + 1;
+        const int64_t cb = std::max<int64_t>(chunk_bound, ncap / p.chunk_cap + p.ntiles + 1);
         if ((s = dev_alloc(&p.d_chunks, sizeof(int4) * cb, &extra)) != BL_OK) return s;
         p.N_cap = ncap;
         p.chunk_alloc = cb;
     }
-    BL_TRY(launch_binning(p, x_dev, N));
+    BL_TRY(bin_tuned(p, x_dev, N));
     p.N = N;
     p.have_nodes = true;
     return BL_OK;
@@ -386,16 +601,29 @@ bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev) {
 bl_status bl_forward(bl_plan plan, const void* fhat_dev, void* f_dev) {
     BL_TRY(check_plan(plan));
     Plan& p = plan->p;
-    if (!p.fft_ok) return fail(BL_EUNSUPPORTED, "bl_forward needs L a power of two, L >= 16 (bl_interpolate takes any even L)");
+    if (!p.fft_ok) return fail(BL_EUNSUPPORTED, "bl_forward: L + M - 1 above the chirp-z LDS size for d >= 2 (bl_interpolate takes any even L)");
     if (!p.have_nodes) return fail(BL_ESTATE, "bl_set_nodes must succeed before bl_forward");
     if (!fhat_dev || (p.N > 0 && !f_dev)) return fail(BL_EINVAL, "NULL buffer");
     if (p.use_graph) {
-        if (!p.fwd_exec || p.fwd_fhat != fhat_dev || p.fwd_f != f_dev)
-            BL_TRY(capture_forward(p, fhat_dev, f_dev));
-        BL_HIP(hipGraphLaunch(p.fwd_exec, p.stream));
+        Plan::FwdGraph* g = nullptr;
+        for (auto& c : p.graphs)
+            if (c.exec && c.fhat == fhat_dev && c.f == f_dev) g = &c;
+        if (!g) BL_TRY(capture_forward(p, fhat_dev, f_dev, &g));
+        g->used = ++p.graph_tick;
+        BL_HIP(hipGraphLaunch(g->exec, p.stream));
     } else {
         BL_TRY(forward_launches(p, fhat_dev, f_dev));
     }
+    p.have_theta = true;
+    return BL_OK;
+}
+
+bl_status bl_samples(bl_plan plan, const void* fhat_dev) {
+    BL_TRY(check_plan(plan));
+    Plan& p = plan->p;
+    if (!p.fft_ok) return fail(BL_EUNSUPPORTED, "bl_samples: L + M - 1 above the chirp-z LDS size for d >= 2");
+    if (!fhat_dev) return fail(BL_EINVAL, "NULL buffer");
+    BL_TRY(launch_forward_fft(p, fhat_dev));
     p.have_theta = true;
     return BL_OK;
 }
@@ -449,7 +677,7 @@ bl_status bl_get_theta(bl_plan plan, void* theta_dev) {
 bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev) {
     BL_TRY(check_plan(plan));
     Plan& p = plan->p;
-    if (!p.fft_ok) return fail(BL_EUNSUPPORTED, "bl_adjoint needs L a power of two, L >= 16");
+    if (!p.fft_ok) return fail(BL_EUNSUPPORTED, "bl_adjoint: L + M - 1 above the chirp-z LDS size for d >= 2");
     if (!p.have_nodes) return fail(BL_ESTATE, "bl_set_nodes must succeed before bl_adjoint");
     if (!fhat_dev || (p.N > 0 && !g_dev)) return fail(BL_EINVAL, "NULL buffer");
     if (!p.d_sgrid) {
@@ -458,7 +686,19 @@ bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev) {
         BL_TRY(dev_alloc(&p.d_sgrid, size_t(p.grid_elems()) * p.cplx_size(), &extra));
         p.workspace_bytes += extra;
     }
-    BL_TRY(launch_spread(p, g_dev, p.d_sgrid));
+    const size_t nb = spread_boxes_bytes(p);
+    if (nb > p.boxes_cap) {
+        BL_HIP(hipStreamSynchronize(p.stream));
+        hipFree(p.d_boxes);
+        p.d_boxes = nullptr;
+        p.workspace_bytes -= p.boxes_cap;
+        p.boxes_cap = 0;
+        size_t extra = 0;
+        BL_TRY(dev_alloc(&p.d_boxes, nb, &extra));
+        p.boxes_cap = nb;
+        p.workspace_bytes += extra;
+    }
+    BL_TRY(launch_spread(p, g_dev, p.d_sgrid, p.d_boxes));
     return launch_adjoint_fft(p, p.d_sgrid, fhat_dev);
 }
 
@@ -484,6 +724,11 @@ bl_status bl_plan_stats(bl_plan plan, bl_stats* out) {
     out->chunk_cap = p.chunk_cap;
     out->workspace_bytes = int64_t(p.workspace_bytes);
     out->beta = p.beta;
+    out->weight_fit_err = p.prec == BL_F64 ? (p.use_poly64 ? p.poly64_err : 0.0) : p.poly_err;
+    for (int i = 0; i < 2; ++i)
+        for (int t = 0; t < 3; ++t) out->fft_lines[i][t] = p.fft_lines[i][t];
+    out->tuned[0] = p.tune_fft_source;
+    out->tuned[1] = p.tune_tile_source;
     return BL_OK;
 }
 

@@ -565,7 +565,7 @@ __device__ __forceinline__ void batch_gather_chunk(const BGatherArgs& a, const i
                              int opaque = 0;
                              asm volatile("" : "+s"(opaque));
                              dev::weights_poly<1, M2, kPolyCoef>(theta, coef + opaque, w, 1.0f);
-                             typename std::conditional<ACC == 1, dev::WideAcc<float>, dev::Plain<float>>::type acc;
+                             dev::OuterAcc<float, ACC> acc;
 #pragma unroll
                              for (int o = 0; o < M2; ++o) acc.add(w[0][o], lds[r + o]);
                              f[nd.out] = acc.value();
@@ -605,34 +605,6 @@ __global__ void k_tile_scan_b(const int32_t* count, int32_t* offset, int32_t* ch
 }
 
 // ---------------------------------------------------------------- host helpers
-// In-place radix-2 DFT (FP64) of a power-of-two length, sign -1: X_q = sum x_n e^{-2 pi i n q/P}.
-void host_dft(std::vector<std::complex<double>>& x, const std::vector<std::complex<double>>& root) {
-    const size_t n = x.size();
-    for (size_t i = 1, j = 0; i < n; ++i) {
-        size_t bit = n >> 1;
-        for (; j & bit; bit >>= 1) j ^= bit;
-        j ^= bit;
-        if (i < j) std::swap(x[i], x[j]);
-    }
-    for (size_t len = 2; len <= n; len <<= 1) {
-        const size_t step = n / len;
-        for (size_t i = 0; i < n; i += len)
-            for (size_t k = 0; k < len / 2; ++k) {
-                const std::complex<double> w = std::conj(root[k * step]);
-                const std::complex<double> u = x[i + k], v = x[i + k + len / 2] * w;
-                x[i + k] = u + v;
-                x[i + k + len / 2] = u - v;
-            }
-    }
-}
-
-// e^{i pi q / L} for integer q (reduced mod 2L in integers, then the twiddle table).
-std::complex<double> chirp(int64_t q, int64_t L, const std::vector<double>& tw2L) {
-    int64_t r = q % (2 * L);
-    if (r < 0) r += 2 * L;
-    return {tw2L[2 * r], tw2L[2 * r + 1]};
-}
-
 int ilog2i(int64_t v) {
     int l = 0;
     while ((int64_t(1) << (l + 1)) <= v) ++l;
@@ -783,6 +755,8 @@ bl_status batch_launches(bl_batch_s* b, hipStream_t s, const void* fhat, void* f
     const size_t lds = ((size_t(b->tile + 2 * kMaxM) * sizeof(CxF) + 15) & ~size_t(15)) +
                        sizeof(float) * kMaxM * kPolyCoef;
     if (b->prec == BL_F32C)
+        hipLaunchKernelGGL(k_batch_gather<2>, dim3(unsigned(b->nchunks)), dim3(256), lds, s, ga);
+    else if (b->prec == BL_F32D)
         hipLaunchKernelGGL(k_batch_gather<1>, dim3(unsigned(b->nchunks)), dim3(256), lds, s, ga);
     else
         hipLaunchKernelGGL(k_batch_gather<0>, dim3(unsigned(b->nchunks)), dim3(256), lds, s, ga);
@@ -937,8 +911,8 @@ bl_status bl_batch_create(bl_batch* out, int count, const int64_t* M, const int6
     if (!out) return bfail(BL_EINVAL, "out is NULL");
     *out = nullptr;
     if (count < 1 || !M || !L || !m || !N) return bfail(BL_EINVAL, "count >= 1 and four host arrays required");
-    if (prec != BL_F32 && prec != BL_F32C)
-        return bfail(prec == BL_F64 ? BL_EUNSUPPORTED : BL_EINVAL, "batched transforms run in BL_F32 or BL_F32C");
+    if (prec != BL_F32 && prec != BL_F32C && prec != BL_F32D)
+        return bfail(prec == BL_F64 ? BL_EUNSUPPORTED : BL_EINVAL, "batched transforms run in float precisions");
     for (int i = 0; i < count; ++i) {
         if (M[i] < 2 || M[i] % 2 || L[i] <= M[i] || L[i] % 2 || m[i] < 1 || 2 * int64_t(m[i]) >= L[i] || N[i] < 0)
             return bfail(BL_EINVAL, "instance " + std::to_string(i) + ": need even M >= 2, even L > M, 2m < L, N >= 0");
@@ -1037,20 +1011,17 @@ bl_status bl_batch_create(bl_batch* out, int count, const int64_t* M, const int6
             post.push_back(double2{c.real(), c.imag()});
         }
         // H = DFT_P(h) / P, h_j = u^{-j^2} at j mod P for |j| < (L + M)/2
-        std::vector<std::complex<double>> h(P, 0.0);
-        const int64_t J = (L[i] + M[i]) / 2;
-        for (int64_t j = -J + 1; j < J; ++j) h[(j % P + P) % P] = std::conj(chirp(j * j, L[i], tw2L));
-        std::vector<double> twp;
-        twiddles(P, &twp);
-        std::vector<std::complex<double>> root(P / 2);
-        for (int64_t k = 0; k < P / 2; ++k) root[k] = {twp[2 * k], twp[2 * k + 1]};
-        host_dft(h, root);
+        const std::vector<std::complex<double>> h = chirp_spectrum(L[i], M[i], P);
         for (int64_t q = 0; q < P; ++q) {
-            hbuf.push_back(float(h[q].real() / double(P)));
-            hbuf.push_back(float(h[q].imag() / double(P)));
+            hbuf.push_back(float(h[q].real()));
+            hbuf.push_back(float(h[q].imag()));
         }
         std::vector<double> pc;
-        fit_weight_polys(BL_WIN_SINH, BL_SHANNON, m[i], beta, kPolyCoef, &pc);
+        const double fit = fit_weight_polys(BL_WIN_SINH, BL_SHANNON, m[i], beta, kPolyCoef, &pc);
+        if (!(fit <= kPolyFitTol))
+            return cleanup(bfail(BL_EUNSUPPORTED, "instance " + std::to_string(i) +
+                                                      ": float weight polynomials fit only to " +
+                                                      std::to_string(fit)));
         for (size_t q = 0; q < pc.size(); ++q) coef[size_t(i) * kMaxM * kPolyCoef + q] = float(pc[q]);
     }
     b->h_node_off[count] = node_off;

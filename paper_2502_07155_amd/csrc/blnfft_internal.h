@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <complex>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -37,6 +38,7 @@ constexpr int kMaxM = 8;
 constexpr int kPolyCoef = 12;   // coefficients of the float weight polynomials (degree 11)
 constexpr int kPolyCoef64 = 16; // coefficients of the double weight polynomials (degree 15)
 constexpr double kDerivFitTol = 5e-12;   // FP64 grad_x from differentiated polynomials (relative)
+constexpr double kPolyFitTol = 1e-7;     // float weight polynomials (relative to the largest weight)
 // Float tiles of the short sums are staged twice (shifted copies, for 128-bit row reads)
 // when the doubled tile still leaves room for several workgroups per CU.
 constexpr bool dual_tiles_for(int d, int m, bool is_float) {
@@ -85,6 +87,34 @@ struct PassShape {
     int L = 0;           // FFT length and outputs per line
 };
 
+// Element types of one FFT pass: input in double, arithmetic in double, output in double,
+// twiddle (and chirp) tables in double with their products formed in double.
+struct PassTypes {
+    bool in64, comp64, out64, tw64;
+};
+
+// Largest chirp-z transform held in LDS by one workgroup (points of the arithmetic type).
+template <typename R>
+constexpr int64_t kCztLdsPoints() { return sizeof(R) == 8 ? 8192 : 16384; }
+
+// Chirp-z (Bluestein) form of the per-axis transforms, for L that the power-of-two passes
+// do not take: cyclic convolutions of power-of-two size P >= L + M - 1.
+struct CztTables {
+    bool on = false;       // the plan's passes use the chirp-z kernels
+    int64_t P = 0;
+    bool split = false;    // one d = 1 line above the LDS size: R pieces of P / R points
+    int R = 1;
+    void* d_roots64 = nullptr;   // e^{2 pi i n / P}, n < P
+    void* d_roots32 = nullptr;
+    void* d_H64 = nullptr;       // H = DFT_P(h) / P
+    void* d_H32 = nullptr;
+    void* d_band64 = nullptr;    // 1/(L psihat1(k)) e^{i pi k^2 / L}, k = i - M/2 (M entries)
+    void* d_band32 = nullptr;
+    void* d_grid64 = nullptr;    // e^{i pi l^2 / L}, l = i - L/2 (L entries)
+    void* d_grid32 = nullptr;
+    void* d_scr = nullptr;       // split path: P complex of the arithmetic type
+};
+
 // Device tables and buffers owned by a plan.
 struct Plan {
     int d = 0;
@@ -104,7 +134,7 @@ struct Plan {
     // Float weight polynomials, [m][kPolyCoef] (even then odd coefficients), and the
     // largest deviation of the fitted weights from the exact ones.
     std::vector<float> poly;
-    double poly_err = 0.0;
+    double poly_err = 0.0;         // refused above kPolyFitTol for float plans
     // The same in double with kPolyCoef64 coefficients (BL_F64 plans), used when the fit
     // is within 1e-13 of the exact weights; otherwise the kernels evaluate them exactly.
     std::vector<double> poly64;
@@ -112,7 +142,12 @@ struct Plan {
     double poly64_deriv_err = 1.0;  // relative error of the polynomials' theta-derivatives
     bool use_poly64 = false;
     double edge_k = 1.0;           // edge exponent of the weight polynomials (edge_exponent)
-    bool fft_ok = true;            // L is a power of two >= 16: steps 1-2 and the adjoint available
+    bool fft_ok = true;            // steps 1-2 and the adjoint available for this L
+    int fft_lines[2][3] = {{0, 0, 0}, {0, 0, 0}};   // [forward, adjoint][axis]: tuned lines per workgroup
+    int tune_fft_source = 0;       // 0 heuristic (or override), 1 measured, 2 from the tuning cache
+    int tune_tile_source = 0;      // the same for the short-sum tiles and chunk capacity
+    int64_t tuned_N = -1;          // node count the tiles were tuned (or looked up) for
+    CztTables czt;                 // chirp-z passes (L not a power of two, or too long)
     void* d_wpre = nullptr;        // precomputed weights (bl_precompute_weights), binned order
     bool use_wpre = false;
     // Inverse-direction twiddles for the adjoint are the conjugates; computed in kernel.
@@ -122,6 +157,8 @@ struct Plan {
     void* d_bufB = nullptr;
     void* d_grid = nullptr;
     void* d_sgrid = nullptr;   // adjoint spreading target (allocated on first bl_adjoint)
+    void* d_boxes = nullptr;   // adjoint: one tile-plus-halo box per chunk (first bl_adjoint)
+    size_t boxes_cap = 0;
     size_t bytes_grid = 0, bytes_A = 0, bytes_B = 0;
 
     // Nodes, sorted by tile.
@@ -136,6 +173,7 @@ struct Plan {
     int chunk_cap = 1024;
     // float tiles of d >= 2 staged twice (shifted copies) for 128-bit row reads
     bool dual_tiles = false;
+    int64_t tile_alloc = 0;        // entries of the four per-tile arrays
     int32_t* d_tile_count = nullptr;
     int32_t* d_tile_offset = nullptr;
     int32_t* d_tile_cursor = nullptr;
@@ -150,15 +188,24 @@ struct Plan {
     bool have_theta = false;
     size_t workspace_bytes = 0;
 
-    // Forward transform captured as a hipGraph (on a private stream) and replayed on
-    // `stream`; valid for one (fhat, f) pointer pair and one node binding.
+    // Forward transform captured as hipGraphs (on a private stream) and replayed on
+    // `stream`: one executable graph per (fhat, f) pointer pair, up to kGraphCache of
+    // them (least recently used evicted), all valid for one node binding.
+    static constexpr int kGraphCache = 4;
+    struct FwdGraph {
+        hipGraphExec_t exec = nullptr;
+        const void* fhat = nullptr;
+        void* f = nullptr;
+        uint64_t used = 0;
+    };
     bool use_graph = true;
     hipStream_t capture_stream = nullptr;
-    hipGraphExec_t fwd_exec = nullptr;
-    const void* fwd_fhat = nullptr;
-    void* fwd_f = nullptr;
+    FwdGraph graphs[kGraphCache];
+    uint64_t graph_tick = 0;
 
     size_t real_size() const { return prec == BL_F64 ? 8 : 4; }
+    // FFT arithmetic in double (F64, and F32D's float data with double passes)
+    bool fft64() const { return prec == BL_F64 || prec == BL_F32D; }
     size_t cplx_size() const { return 2 * real_size(); }
     int64_t grid_elems() const {
         int64_t g = 1;
@@ -183,6 +230,13 @@ void window_transform_ints(bl_window win, bl_method method, int64_t L, int m, do
 // e^{2 pi i n / L} for n in [0, L), correctly reduced; interleaved (re, im).
 void twiddles(int64_t L, std::vector<double>* out);
 bool factor_length(int L, int E, FftFactors* out);
+// In-place FP64 radix-2 DFT with kernel e^{-2 pi i n q / P} (root[k] = e^{2 pi i k/P}, k < P/2).
+void host_dft(std::vector<std::complex<double>>& x, const std::vector<std::complex<double>>& root);
+// e^{i pi q / L} for integer q, reduced mod 2L in integers (tw2L = twiddles(2L)).
+std::complex<double> chirp(int64_t q, int64_t L, const std::vector<double>& tw2L);
+// Chirp-z convolution kernel spectrum H = DFT_P(h) / P of h_j = e^{-i pi j^2 / L} at cyclic
+// position j mod P, |j| < (L + M)/2 (zero elsewhere), FP64; P >= L + M - 1, a power of two.
+std::vector<std::complex<double>> chirp_spectrum(int64_t L, int64_t M, int64_t P);
 void stage_twiddles(const FftFactors& fac, const std::vector<double>& tw, std::vector<double>* out,
                     int* off);
 double window_value(bl_window win, bl_method method, int m, double beta, double u);
@@ -205,8 +259,25 @@ bl_status launch_gather(Plan& p, const void* theta, void* f);
 bl_status launch_weights(Plan& p);
 // Binning of nodes.
 bl_status launch_binning(Plan& p, const void* x, int64_t N);
-// Adjoint spreading Psi^T g (or B^T g) onto `grid` (L^d, centred), which it overwrites.
-bl_status launch_spread(Plan& p, const void* g, void* grid);
+// Adjoint spreading Psi^T g (or B^T g) onto `grid` (L^d, centred), which it overwrites:
+// per-chunk boxes into `boxes` (spread_boxes_bytes), then their fixed-order merge.
+bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes);
+size_t spread_boxes_bytes(const Plan& p);
+// One chirp-z pass (czt.hip): lines outer x inner, Min inputs and Mout outputs per line in
+// centred order; dir +1 forward (band -> grid), -1 adjoint (grid -> band).
+bl_status launch_czt_pass(Plan& p, int dir, const void* in, void* out, int outer, int inner, int Min,
+                          int Mout, PassTypes t, int lines);
+// Autotuner (fft.hip): time every forward and adjoint pass of the plan for 1, 2, ..., 16
+// lines per workgroup on the given scratch buffers (each >= L^d complex of the pass type)
+// and keep the fastest in p.fft_lines.
+bl_status tune_fft_lines(Plan& p, void* buf_in, void* buf_out);
+// autotune.cpp: FFT lines per workgroup at plan creation (cached), and the cache of the
+// short-sum tile edge and chunk capacity measured at the first large node binding.
+constexpr int64_t kTuneMinNodes = int64_t(1) << 16;
+bl_status autotune_fft(Plan& p);
+bool tile_tuning_wanted(const Plan& p, int64_t N);
+bool tile_cache_lookup(const Plan& p, int density, int cluster, int* T, int* cap);
+void tile_cache_store(const Plan& p, int density, int cluster, int T, int cap);
 // Node gradient from the plan's grid.
 bl_status launch_grad_x(Plan& p, const void* g, void* gx);
 

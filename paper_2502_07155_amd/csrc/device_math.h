@@ -371,6 +371,37 @@ struct WideAcc {
     __device__ __forceinline__ Cx<R> value() const { return {R(re), R(im)}; }
 };
 
+// Compensated accumulation of float terms: each product w v is rounded once, and every
+// addition to the running sum is made error-free by Knuth's two-sum (s + t = s' + e exactly,
+// e formed from s, t and s' in six float operations); the errors are summed separately and
+// added once at the end.  For double data it is the plain FMA sum.
+template <typename R>
+struct TwoSumAcc {
+    R re = R(0), im = R(0), cre = R(0), cim = R(0);
+    __device__ __forceinline__ static void two_sum(R& s, R t, R& c) {
+        const R s1 = s + t;
+        const R bp = s1 - s;
+        const R ap = s1 - bp;
+        c += (s - ap) + (t - bp);
+        s = s1;
+    }
+    __device__ __forceinline__ void add(R w, Cx<R> v) {
+        if constexpr (std::is_same<R, double>::value) {
+            re = dev_fma(w, v.re, re);
+            im = dev_fma(w, v.im, im);
+        } else {
+            two_sum(re, w * v.re, cre);
+            two_sum(im, w * v.im, cim);
+        }
+    }
+    __device__ __forceinline__ Cx<R> value() const { return {re + cre, im + cim}; }
+};
+
+// Accumulator of the outermost short-sum loop: 0 plain FMA sums, 1 double (WideAcc),
+// 2 two-sum compensated (TwoSumAcc).
+template <typename R, int ACC>
+using OuterAcc = typename std::conditional<ACC == 1, WideAcc<R>,
+                 typename std::conditional<ACC == 2, TwoSumAcc<R>, Plain<R>>::type>::type;
 
 }  // namespace dev
 }  // namespace bl

@@ -12,10 +12,14 @@
 //    centred index (q + L/2) mod L.  Axes not yet transformed keep extent M (pruning).
 //  * Adjoint pass (dir -1): input in centred order, output the M band entries times the
 //    factor.  Axes already transformed have extent M.
-//  * Precision: BL_F64 and BL_F32 compute and store in their own type.  BL_F32C reads
-//    float, computes in double (LDS and registers; FP64 runs at the FP32 vector rate on
-//    this GPU when packed FP32 is not used), keeps the pass intermediates in double and
-//    rounds once, when the grid of samples (or the output band) is stored as float.
+//  * Precision: BL_F64 and BL_F32 compute and store in their own type.  BL_F32C computes
+//    and stores in float but keeps the twiddles in FP64: each twiddle product is formed in
+//    double and rounded once (as the deconvolution factors are for every precision).
+//    BL_F32D reads float, computes in double (LDS and registers; FP64 runs at the FP32
+//    vector rate on this GPU when packed FP32 is not used), keeps the pass intermediates
+//    in double and rounds once, when the grid of samples (or the output band) is stored.
+//  * L that is not a power of two (or a d = 1 line longer than the LDS pass takes) runs
+//    the chirp-z passes of czt.hip instead, with the same layouts and factors.
 #include <cstdlib>
 
 #include "blnfft_internal.h"
@@ -41,6 +45,7 @@ struct PassArgs {
     int nmain;              // stages of the main radix E (the plan is E, ..., E, rlast)
     int rlast;              // trailing radix (2, 4 or 8 for E = 16; 2 for E = 4), 1 for none
     int tw_off[kMaxStages];
+    int lines;              // lines per workgroup chosen by the autotuner (0: heuristic)
 };
 
 // Butterfly g of a stage -> (line b, butterfly index j within the line).  Contiguous
@@ -173,8 +178,8 @@ __device__ __forceinline__ void stage_read(Cx<R>* reg, const Cx<R>* lds, const I
     }
 }
 
-template <typename R, int E, int DIR, int RAD, bool CONTIG, int DST, typename IO>
-__device__ __forceinline__ void stage_write(Cx<R>* reg, Cx<R>* lds, const Cx<R>* __restrict__ tw,
+template <typename R, typename TW, int E, int DIR, int RAD, bool CONTIG, int DST, typename IO>
+__device__ __forceinline__ void stage_write(Cx<R>* reg, Cx<R>* lds, const Cx<TW>* __restrict__ tw,
                                             const IO& io, int lgL, int lgB, int Lp, int Ns,
                                             int tid, int NT) {
     constexpr int NB = E / RAD;
@@ -187,12 +192,12 @@ __device__ __forceinline__ void stage_write(Cx<R>* reg, Cx<R>* lds, const Cx<R>*
         const int k = j & (Ns - 1);
         Cx<R>* a = reg + u * RAD;
         if (Ns > 1) {
-            const Cx<R>* wk = tw + k * (RAD - 1);
+            const Cx<TW>* wk = tw + k * (RAD - 1);
 #pragma unroll
             for (int r = 1; r < RAD; ++r) {
-                Cx<R> w = wk[r - 1];
+                Cx<TW> w = wk[r - 1];
                 if (DIR < 0) w.im = -w.im;
-                a[r] = cmul(a[r], w);
+                a[r] = mulw<R, TW>(a[r], w);
             }
         }
         dft<R, DIR, RAD>(a);
@@ -207,11 +212,11 @@ __device__ __forceinline__ void stage_write(Cx<R>* reg, Cx<R>* lds, const Cx<R>*
 }
 
 // Last stage (LDS -> HBM) of radix RAD.
-template <typename R, int E, int DIR, int RAD, bool CONTIG, typename IO>
-__device__ __forceinline__ void last_stage(Cx<R>* reg, Cx<R>* lds, const Cx<R>* tw, const IO& io,
+template <typename R, typename TW, int E, int DIR, int RAD, bool CONTIG, typename IO>
+__device__ __forceinline__ void last_stage(Cx<R>* reg, Cx<R>* lds, const Cx<TW>* tw, const IO& io,
                                            int lgL, int lgB, int Lp, int Ns, int tid, int NT) {
     stage_read<R, E, RAD, CONTIG, 0>(reg, lds, io, lgL, lgB, Lp, tid, NT);
-    stage_write<R, E, DIR, RAD, CONTIG, 1>(reg, lds, tw, io, lgL, lgB, Lp, Ns, tid, NT);
+    stage_write<R, TW, E, DIR, RAD, CONTIG, 1>(reg, lds, tw, io, lgL, lgB, Lp, Ns, tid, NT);
 }
 
 // Threads per workgroup: 1024 with four values per thread, 512 with sixteen (register
@@ -219,9 +224,10 @@ __device__ __forceinline__ void last_stage(Cx<R>* reg, Cx<R>* lds, const Cx<R>* 
 template <int E>
 constexpr int max_threads() { return E == 4 ? 1024 : 512; }
 
-// TI: input element type, R: LDS / arithmetic type, TO: output element type, E: values per
-// thread (= the main radix: 16, or 4 when the pass has few lines and needs more threads).
-template <typename TI, typename R, typename TO, int DIR, bool CONTIG, int E>
+// TI: input element type, R: LDS / arithmetic type, TO: output element type, TW: twiddle
+// type (products formed in it), E: values per thread (= the main radix: 16, or 4 when the
+// pass has few lines and needs more threads).
+template <typename TI, typename R, typename TO, typename TW, int DIR, bool CONTIG, int E>
 __global__ void __launch_bounds__(max_threads<E>()) k_fft_pass(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x;
@@ -230,7 +236,7 @@ __global__ void __launch_bounds__(max_threads<E>()) k_fft_pass(PassArgs a) {
     const int L = a.L;
     const int Lp = padpos(L - 1) + 1;
     Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
-    const Cx<R>* tw = static_cast<const Cx<R>*>(a.tw);
+    const Cx<TW>* tw = static_cast<const Cx<TW>*>(a.tw);
     const int blk = xcd_block(int(blockIdx.x), int(gridDim.x));
 
     LineIO<TI, R, TO, DIR, CONTIG> io;
@@ -258,9 +264,9 @@ __global__ void __launch_bounds__(max_threads<E>()) k_fft_pass(PassArgs a) {
     if (a.factor) stage_read<R, E, E, CONTIG, 1, decltype(io), true>(reg, lds, io, a.lgL, a.lgB, Lp, tid, NT);
     else stage_read<R, E, E, CONTIG, 1, decltype(io), false>(reg, lds, io, a.lgL, a.lgB, Lp, tid, NT);
     if (a.tw_in_lds) {
-        Cx<R>* twl = lds + size_t(B) * Lp;
+        Cx<TW>* twl = reinterpret_cast<Cx<TW>*>(lds + size_t(B) * Lp);
         for (int e0 = tid; e0 < a.tw_len; e0 += 4 * NT) {
-            Cx<R> v[4];
+            Cx<TW> v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) v[u] = tw[min(e0 + u * NT, a.tw_len - 1)];
 #pragma unroll
@@ -271,10 +277,10 @@ __global__ void __launch_bounds__(max_threads<E>()) k_fft_pass(PassArgs a) {
     }
     const int nstages = a.nmain + (a.rlast > 1 ? 1 : 0);
     if (nstages == 1) {
-        stage_write<R, E, DIR, E, CONTIG, 1>(reg, lds, tw, io, a.lgL, a.lgB, Lp, 1, tid, NT);
+        stage_write<R, TW, E, DIR, E, CONTIG, 1>(reg, lds, tw, io, a.lgL, a.lgB, Lp, 1, tid, NT);
         return;
     }
-    stage_write<R, E, DIR, E, CONTIG, 0>(reg, lds, tw, io, a.lgL, a.lgB, Lp, 1, tid, NT);
+    stage_write<R, TW, E, DIR, E, CONTIG, 0>(reg, lds, tw, io, a.lgL, a.lgB, Lp, 1, tid, NT);
     __syncthreads();
     int Ns = E;
     // middle radix-E stages, LDS -> LDS in place
@@ -282,21 +288,21 @@ __global__ void __launch_bounds__(max_threads<E>()) k_fft_pass(PassArgs a) {
     for (int s = 1; s <= nmid; ++s) {
         stage_read<R, E, E, CONTIG, 0>(reg, lds, io, a.lgL, a.lgB, Lp, tid, NT);
         __syncthreads();
-        stage_write<R, E, DIR, E, CONTIG, 0>(reg, lds, tw + a.tw_off[s], io, a.lgL, a.lgB, Lp, Ns, tid, NT);
+        stage_write<R, TW, E, DIR, E, CONTIG, 0>(reg, lds, tw + a.tw_off[s], io, a.lgL, a.lgB, Lp, Ns, tid, NT);
         __syncthreads();
         Ns *= E;
     }
-    const Cx<R>* twl = tw + a.tw_off[nstages - 1];
+    const Cx<TW>* twl = tw + a.tw_off[nstages - 1];
     if constexpr (E == 16) {
         switch (a.rlast) {
-            case 2: last_stage<R, E, DIR, 2, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
-            case 4: last_stage<R, E, DIR, 4, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
-            case 8: last_stage<R, E, DIR, 8, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
-            default: last_stage<R, E, DIR, 16, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
+            case 2: last_stage<R, TW, E, DIR, 2, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
+            case 4: last_stage<R, TW, E, DIR, 4, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
+            case 8: last_stage<R, TW, E, DIR, 8, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
+            default: last_stage<R, TW, E, DIR, 16, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT); break;
         }
     } else {
-        if (a.rlast == 2) last_stage<R, E, DIR, 2, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT);
-        else last_stage<R, E, DIR, E, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT);
+        if (a.rlast == 2) last_stage<R, TW, E, DIR, 2, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT);
+        else last_stage<R, TW, E, DIR, E, CONTIG>(reg, lds, twl, io, a.lgL, a.lgB, Lp, Ns, tid, NT);
     }
 }
 
@@ -310,7 +316,7 @@ int ilog2(int v) {
 // max_threads, and LDS within 96 KB.  Contiguous passes need no line grouping for
 // coalescing, so there B is halved while the pass would have fewer workgroups than CUs
 // (measured: 512 lines of 1024 points run faster as 256 workgroups of 2 than 128 of 4).
-int choose_lines(const Plan& p, size_t c, int E, bool contiguous, int64_t lines) {
+int choose_lines(const Plan& p, size_t c, int E, bool contiguous, int64_t lines, int tuned) {
     const int L = int(p.L);
     const int bmax = (c == 16) ? 8 : 16;
     const int tmax = E == 4 ? 1024 : 512;
@@ -321,6 +327,7 @@ int choose_lines(const Plan& p, size_t c, int E, bool contiguous, int64_t lines)
     constexpr int64_t kCUs = 256;
     if (contiguous)
         while (b > 1 && (lines + b - 1) / b < kCUs) b /= 2;
+    if (tuned > 0) b = tuned;   // measured at plan creation (autotune.cpp)
     if (const char* e = std::getenv("BL_FFT_LINES")) {   // tuning override
         const int v = std::atoi(e);
         if (v >= 1 && v <= 64 && (v & (v - 1)) == 0) b = v;
@@ -347,16 +354,16 @@ int choose_radix(const Plan& p, int64_t lines) {
     return 4;
 }
 
-template <typename TI, typename R, typename TO, int DIR, int E>
+template <typename TI, typename R, typename TO, typename TW, int DIR, int E>
 bl_status run_pass_e(Plan& p, PassArgs a) {
     const bool contiguous = (a.inner == 1);
-    const int B = choose_lines(p, sizeof(Cx<R>), E, contiguous, int64_t(a.outer) * a.inner);
+    const int B = choose_lines(p, sizeof(Cx<R>), E, contiguous, int64_t(a.outer) * a.inner, a.lines);
     a.lgB = ilog2(B);
     a.lgL = ilog2(a.L);
     const int L = a.L;
     const int NT = int((int64_t(B) * L) / E);
     const size_t data = size_t(B) * size_t(padpos(L - 1) + 1) * sizeof(Cx<R>);
-    const size_t twb = size_t(a.tw_len) * sizeof(Cx<R>);
+    const size_t twb = size_t(a.tw_len) * sizeof(Cx<TW>);
     a.tw_in_lds = (twb <= 32 * 1024 && data + twb <= 160 * 1024) ? 1 : 0;
     const size_t lds = data + (a.tw_in_lds ? twb : 0);
     if (NT > max_threads<E>() || lds > 160 * 1024) {
@@ -370,7 +377,7 @@ bl_status run_pass_e(Plan& p, PassArgs a) {
         set_error("FFT pass grid too large");
         return BL_EUNSUPPORTED;
     }
-    auto kern = contiguous ? k_fft_pass<TI, R, TO, DIR, true, E> : k_fft_pass<TI, R, TO, DIR, false, E>;
+    auto kern = contiguous ? k_fft_pass<TI, R, TO, TW, DIR, true, E> : k_fft_pass<TI, R, TO, TW, DIR, false, E>;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    int(lds)));
@@ -379,7 +386,7 @@ bl_status run_pass_e(Plan& p, PassArgs a) {
     return BL_OK;
 }
 
-template <typename TI, typename R, typename TO, int DIR>
+template <typename TI, typename R, typename TO, typename TW, int DIR>
 bl_status run_pass(Plan& p, PassArgs a) {
     const int64_t lines = int64_t(a.outer) * a.inner;
     const int E = choose_radix(p, lines);
@@ -387,34 +394,35 @@ bl_status run_pass(Plan& p, PassArgs a) {
     a.nmain = st.nmain;
     a.rlast = st.rlast;
     for (int s = 0; s < kMaxStages; ++s) a.tw_off[s] = st.tw_off[s];
-    a.tw = sizeof(R) == 8 ? st.d_tw64 : st.d_tw32;
+    a.tw = sizeof(TW) == 8 ? st.d_tw64 : st.d_tw32;
     a.tw_len = st.tw_len;
-    if (E == 16) return run_pass_e<TI, R, TO, DIR, 16>(p, a);
-    return run_pass_e<TI, R, TO, DIR, 4>(p, a);
+    if (E == 16) return run_pass_e<TI, R, TO, TW, DIR, 16>(p, a);
+    return run_pass_e<TI, R, TO, TW, DIR, 4>(p, a);
 }
 
-// Element types of one pass.  F64: all double.  F32: all float.  F32C: float input and
-// output at the ends of the chain, double arithmetic in LDS and double intermediates
-// between passes (a single rounding to float, at the final store).
-struct PassTypes {
-    bool in64, comp64, out64;
-};
-
+// Element types of one pass.  F64: all double.  F32: all float.  F32C: float data and
+// arithmetic, FP64 twiddles.  F32D: float input and output at the ends of the chain,
+// double arithmetic in LDS and double intermediates between passes (a single rounding to
+// float, at the final store).
 PassTypes pass_types(const Plan& p, bool first, bool last) {
-    if (p.prec == BL_F64) return {true, true, true};
-    if (p.prec == BL_F32) return {false, false, false};
-    return {!first, true, !last};
+    if (p.prec == BL_F64) return {true, true, true, true};
+    if (p.prec == BL_F32) return {false, false, false, false};
+    if (p.prec == BL_F32C) return {false, false, false, true};
+    return {!first, true, !last, true};
 }
 
 template <int DIR>
 bl_status dispatch_pass(Plan& p, const PassArgs& a, PassTypes t) {
+    if (p.czt.on)
+        return launch_czt_pass(p, DIR, a.in, a.out, a.outer, a.inner, a.Min, a.Mout, t, a.lines);
     if (t.comp64) {
-        if (t.in64 && t.out64) return run_pass<double, double, double, DIR>(p, a);
-        if (!t.in64 && t.out64) return run_pass<float, double, double, DIR>(p, a);
-        if (t.in64 && !t.out64) return run_pass<double, double, float, DIR>(p, a);
-        return run_pass<float, double, float, DIR>(p, a);
+        if (t.in64 && t.out64) return run_pass<double, double, double, double, DIR>(p, a);
+        if (!t.in64 && t.out64) return run_pass<float, double, double, double, DIR>(p, a);
+        if (t.in64 && !t.out64) return run_pass<double, double, float, double, DIR>(p, a);
+        return run_pass<float, double, float, double, DIR>(p, a);
     }
-    return run_pass<float, float, float, DIR>(p, a);
+    if (t.tw64) return run_pass<float, float, float, double, DIR>(p, a);
+    return run_pass<float, float, float, float, DIR>(p, a);
 }
 
 void fill_common(const Plan& p, PassArgs& a) {
@@ -441,6 +449,7 @@ bl_status forward_fft(Plan& p, const void* fhat) {
         for (int k = axis + 1; k < d; ++k) a.inner *= int(p.L);
         a.Min = int(p.M);
         a.Mout = int(p.L);
+        a.lines = p.fft_lines[0][axis];
         BL_TRY(dispatch_pass<+1>(p, a, t));
         src = dst;
     }
@@ -465,13 +474,71 @@ bl_status adjoint_fft(Plan& p, const void* grid, void* fhat_out) {
         for (int k = axis + 1; k < d; ++k) a.inner *= int(p.M);
         a.Min = int(p.L);
         a.Mout = int(p.M);
+        a.lines = p.fft_lines[1][axis];
         BL_TRY(dispatch_pass<-1>(p, a, t));
         src = dst;
     }
     return BL_OK;
 }
 
+// Average time (ms) of `reps` launches of one pass with `lines` lines per workgroup; a
+// negative value when that line count is not valid for the pass.
+template <int DIR>
+double time_pass(Plan& p, PassArgs a, PassTypes t, int lines, int reps, hipEvent_t e0, hipEvent_t e1) {
+    a.lines = lines;
+    if (dispatch_pass<DIR>(p, a, t) != BL_OK) return -1.0;   // warm-up (and validity)
+    if (hipEventRecord(e0, p.stream) != hipSuccess) return -1.0;
+    for (int r = 0; r < reps; ++r)
+        if (dispatch_pass<DIR>(p, a, t) != BL_OK) return -1.0;
+    if (hipEventRecord(e1, p.stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+    return double(ms) / reps;
+}
+
 }  // namespace
+
+bl_status tune_fft_lines(Plan& p, void* buf_in, void* buf_out) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BL_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        set_error("hipEventCreate failed");
+        return BL_EDEVICE;
+    }
+    const int d = p.d;
+    for (int dir = 0; dir < 2; ++dir) {
+        for (int axis = d - 1; axis >= 0; --axis) {
+            const PassTypes t = pass_types(p, axis == d - 1, axis == 0);
+            PassArgs a{};
+            a.in = buf_in;
+            a.out = buf_out;
+            fill_common(p, a);
+            a.outer = 1;
+            a.inner = 1;
+            for (int k = 0; k < axis; ++k) a.outer *= int(dir == 0 ? p.M : p.L);
+            for (int k = axis + 1; k < d; ++k) a.inner *= int(dir == 0 ? p.L : p.M);
+            a.Min = int(dir == 0 ? p.M : p.L);
+            a.Mout = int(dir == 0 ? p.L : p.M);
+            int best = 0;
+            double best_ms = 0.0;
+            for (int lines = 1; lines <= 16; lines *= 2) {
+                const double ms = dir == 0 ? time_pass<+1>(p, a, t, lines, 5, e0, e1)
+                                           : time_pass<-1>(p, a, t, lines, 5, e0, e1);
+                if (ms > 0.0 && (best == 0 || ms < best_ms)) {
+                    best = lines;
+                    best_ms = ms;
+                }
+            }
+            (void)hipGetLastError();
+            p.fft_lines[dir][axis] = best;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    set_error("");
+    return BL_OK;
+}
 
 bl_status launch_forward_fft(Plan& p, const void* fhat) { return forward_fft(p, fhat); }
 

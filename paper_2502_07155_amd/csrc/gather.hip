@@ -58,8 +58,8 @@ __device__ __forceinline__ int node_tile_of(const BinArgs& a, const R* x, int64_
 }
 
 // Binning with per-workgroup LDS histograms.  A workgroup takes kBinPer * kBinThreads
-// consecutive nodes (their tiles stay in registers) and walks the tiles in windows of
-// kLdsBins: it counts its nodes of the window in LDS, then adds each nonzero count to the
+// consecutive nodes (their tiles stay in registers) and walks the tiles between its
+// smallest and largest in windows of kLdsBins: it counts its nodes of the window in LDS, then adds each nonzero count to the
 // global counter once, instead of one contended global atomic per node.  The domain flags
 // are summed per wave first.  The scatter recounts the same nodes window by window, keeping
 // each node's LDS rank, reserves one range per tile with a single global atomic and places
@@ -67,6 +67,37 @@ __device__ __forceinline__ int node_tile_of(const BinArgs& a, const R* x, int64_
 constexpr int kLdsBins = 8192;
 constexpr int kBinThreads = 256;
 constexpr int kBinPer = 16;
+
+// Smallest and largest tile among the workgroup's nodes (tl < 0: no node); the windows
+// of kLdsBins tiles outside [lo, hi] hold none of them and are skipped.  Uniform over the
+// workgroup (read from LDS after a barrier); hi < lo when the workgroup has no nodes.
+__device__ __forceinline__ void tile_range(const int* tl, int& lo, int& hi) {
+    __shared__ int s_lo, s_hi;
+    if (threadIdx.x == 0) {
+        s_lo = 0x7fffffff;
+        s_hi = -1;
+    }
+    int a = 0x7fffffff, b = -1;
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k) {
+        if (tl[k] >= 0) {
+            a = min(a, tl[k]);
+            b = max(b, tl[k]);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a = min(a, __shfl_xor(a, off));
+        b = max(b, __shfl_xor(b, off));
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0 && b >= 0) {
+        atomicMin(&s_lo, a);
+        atomicMax(&s_hi, b);
+    }
+    __syncthreads();
+    lo = s_lo;
+    hi = s_hi;
+}
 
 template <typename R, int D>
 __global__ void __launch_bounds__(kBinThreads) k_bin_count(BinArgs a, int ntiles) {
@@ -95,7 +126,9 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_count(BinArgs a, int ntiles
         if (nbad) atomicAdd(&a.flags[0], (unsigned long long)nbad);
         if (nout) atomicAdd(&a.flags[1], (unsigned long long)nout);
     }
-    for (int w0 = 0; w0 < ntiles; w0 += kLdsBins) {
+    int tlo, thi;
+    tile_range(tl, tlo, thi);
+    for (int w0 = thi < 0 ? ntiles : (tlo / kLdsBins) * kLdsBins; w0 <= thi && w0 < ntiles; w0 += kLdsBins) {
         const int nw = min(kLdsBins, ntiles - w0);
         __syncthreads();   // previous window flushed
         for (int e = threadIdx.x; e < nw; e += kBinThreads) hist[e] = 0;
@@ -161,7 +194,9 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(const R* __restrict
         tl[k] = j < N ? node_tile[j] : -1;
         rank[k] = 0;
     }
-    for (int w0 = 0; w0 < ntiles; w0 += kLdsBins) {
+    int tlo, thi;
+    tile_range(tl, tlo, thi);
+    for (int w0 = thi < 0 ? ntiles : (tlo / kLdsBins) * kLdsBins; w0 <= thi && w0 < ntiles; w0 += kLdsBins) {
         const int nw = min(kLdsBins, ntiles - w0);
         __syncthreads();   // previous window placed
         for (int e = threadIdx.x; e < nw; e += kBinThreads) hist[e] = 0;
@@ -489,9 +524,10 @@ __global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
             for (int t = 0; t < D; ++t)
                 weights<R, M2, METHOD>(theta[t], R(a.beta), R(a.cb), R(1) / R(m * m), w[t]);
         }
-        // Separable contraction: plain FMA sums along the last dimension(s); with ACC == 1
-        // the outermost sum is accumulated in double (float products are exact there).
-        using Outer = typename std::conditional<ACC == 1, WideAcc<R>, Plain<R>>::type;
+        // Separable contraction: plain FMA sums along the last dimension(s); the outermost
+        // sum is plain (ACC 0), accumulated in double (ACC 1: float products are exact
+        // there) or compensated by two-sums (ACC 2).
+        using Outer = OuterAcc<R, ACC>;
         Cx<R> res;
         if constexpr (D == 1) {
             Outer acc;
@@ -596,6 +632,7 @@ GatherFn pick_gather(const Plan& p) {
     if (p.use_wpre && !M) {   // precomputed weights: Algorithm 4.2 only
         if (p.prec == BL_F64) return pick_d<double, 0, 0, true>(p.d, p.m);
         if (p.prec == BL_F32) return pick_d<float, 0, 0, true>(p.d, p.m);
+        if (p.prec == BL_F32C) return pick_d<float, 2, 0, true>(p.d, p.m);
         return pick_d<float, 1, 0, true>(p.d, p.m);
     }
     if (p.prec == BL_F64) {
@@ -604,6 +641,8 @@ GatherFn pick_gather(const Plan& p) {
     }
     if (p.prec == BL_F32)
         return M ? pick_d<float, 0, 1>(p.d, p.m) : pick_d<float, 0, 0>(p.d, p.m);
+    if (p.prec == BL_F32C)
+        return M ? pick_d<float, 2, 1>(p.d, p.m) : pick_d<float, 2, 0>(p.d, p.m);
     return M ? pick_d<float, 1, 1>(p.d, p.m) : pick_d<float, 1, 0>(p.d, p.m);
 }
 

@@ -2,6 +2,7 @@
 // twiddle factors and FFT factorisations.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <vector>
 
@@ -161,6 +162,49 @@ void twiddles(int64_t L, std::vector<double>* out) {
         (*out)[2 * n] = re;
         (*out)[2 * n + 1] = im;
     }
+}
+
+// In-place radix-2 DFT (FP64) of a power-of-two length, sign -1: X_q = sum x_n e^{-2 pi i n q/P};
+// root[k] = e^{2 pi i k / P}, k < P/2.
+void host_dft(std::vector<std::complex<double>>& x, const std::vector<std::complex<double>>& root) {
+    const size_t n = x.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(x[i], x[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        const size_t step = n / len;
+        for (size_t i = 0; i < n; i += len)
+            for (size_t k = 0; k < len / 2; ++k) {
+                const std::complex<double> w = std::conj(root[k * step]);
+                const std::complex<double> u = x[i + k], v = x[i + k + len / 2] * w;
+                x[i + k] = u + v;
+                x[i + k + len / 2] = u - v;
+            }
+    }
+}
+
+std::complex<double> chirp(int64_t q, int64_t L, const std::vector<double>& tw2L) {
+    int64_t r = q % (2 * L);
+    if (r < 0) r += 2 * L;
+    return {tw2L[2 * r], tw2L[2 * r + 1]};
+}
+
+std::vector<std::complex<double>> chirp_spectrum(int64_t L, int64_t M, int64_t P) {
+    std::vector<double> tw2L;
+    twiddles(2 * L, &tw2L);
+    std::vector<std::complex<double>> h(P, 0.0);
+    const int64_t J = (L + M) / 2;
+    for (int64_t j = -J + 1; j < J; ++j) h[(j % P + P) % P] = std::conj(chirp(j * j, L, tw2L));
+    std::vector<double> twp;
+    twiddles(P, &twp);
+    std::vector<std::complex<double>> root(P / 2);
+    for (int64_t k = 0; k < P / 2; ++k) root[k] = {twp[2 * k], twp[2 * k + 1]};
+    host_dft(h, root);
+    for (auto& v : h) v /= double(P);
+    return h;
 }
 
 // Regularized sinc psi_g(u) (shannon) or window phi_g(u) (nfft) in grid units, u = L x - l.

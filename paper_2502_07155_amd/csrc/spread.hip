@@ -1,16 +1,19 @@
 // Adjoint spreading (Psi^T g of the factorisation (4.11), or B^T g for Algorithm 2.1) and
 // the node gradient d f_j / d x_jt of the short sums (4.8).
 //
-// Spreading runs one workgroup per binning chunk (all its nodes share one tile): each
-// node adds g_j psi(x_j - l/L) to the (2m)^d cells around it in an LDS copy of the tile
-// plus halo (LDS atomics), and the workgroup then adds that copy to the grid in HBM with
-// hardware float atomics.  Cells outside I_L are dropped (Psi has columns l in I_L only)
-// or wrapped (periodic B).  Summation order across threads is not fixed, so results can
-// differ in the last bits between runs.
+// Spreading runs one workgroup per binning chunk (all its nodes share one tile): the
+// contributions g_j psi(x_j - l/L) of the chunk's nodes to the (2m)^d cells around each of
+// them are accumulated over the chunk's box (tile plus halo) and the box is written to the
+// chunk's slot of a box buffer.  A merge kernel then forms every grid point as the sum of
+// the box entries that cover it, visiting tiles, and the chunks of each tile, in a fixed
+// order: no float atomics reach HBM, and for one node binding repeated adjoints are
+// bitwise equal.  Box cells outside I_L are dropped (Psi has columns l in I_L only) or
+// wrapped (periodic B).
 //
 // The gradient kernel mirrors the short-sum kernel, with psi' in one dimension:
 //   d f_j / d x_jt = L sum_l theta_l psi_g'(u_t) prod_{s != t} psi_g(u_s).
 #include <cstdlib>
+#include <string>
 
 #include "blnfft_internal.h"
 #include "device_math.h"
@@ -45,18 +48,17 @@ struct SpreadArgs {
     alignas(16) double poly64[kMaxM * kPolyCoef64];   // double weight polynomials
     int use_poly64;          // double kernels: weights from poly64 instead of the exact form
     float edge_k;            // edge exponent of the weight polynomials
+    void* boxes;             // spreading: one box (prod_t (tile_t + 2m - 1) complex) per chunk
+    int64_t box_vol;         // complex entries per box
 };
-
-template <typename R>
-__global__ void k_zero(Cx<R>* p, int64_t n) {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = Cx<R>{R(0), R(0)};
-}
 
 __device__ __forceinline__ void lds_add(float* p, float v) { atomicAdd(p, v); }
 __device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
-__device__ __forceinline__ void hbm_add(float* p, float v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void hbm_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+// Entry e (row-major over the box extents) of the box of chunk ci.
+template <typename R>
+__device__ __forceinline__ void box_store(const SpreadArgs& a, int ci, int e, Cx<R> v) {
+    static_cast<Cx<R>*>(a.boxes)[int64_t(ci) * a.box_vol + e] = v;
+}
 
 template <int D>
 __device__ __forceinline__ void tile_geometry(const int4& ch, const int* tpd, const int* tile,
@@ -148,31 +150,8 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
     }
     __syncthreads();
 
-    R* __restrict__ grid = static_cast<R*>(a.grid);
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const R vre = acc[2 * e], vim = acc[2 * e + 1];
-        if (vre == R(0) && vim == R(0)) continue;
-        int rem = e;
-        int64_t gidx = 0;
-        bool ok = true;
-#pragma unroll
-        for (int t = D - 1; t >= 0; --t) {
-            int ct = rem % W[t];
-            rem /= W[t];
-            int p = n0[t] - m + 1 + ct;
-            if (METHOD == 1) {
-                p = (p % L + L) % L;
-            } else if (p < 0 || p >= L) {
-                ok = false;
-            }
-            int64_t st = 1;
-            for (int s = t + 1; s < D; ++s) st *= L;
-            gidx += int64_t(p) * st;
-        }
-        if (!ok) continue;
-        hbm_add(grid + 2 * gidx, vre);
-        hbm_add(grid + 2 * gidx + 1, vim);
-    }
+    const int ci = xcd_block(int(blockIdx.x), int(gridDim.x));
+    for (int e = threadIdx.x; e < total; e += blockDim.x) box_store<R>(a, ci, e, Cx<R>{acc[2 * e], acc[2 * e + 1]});
 }
 
 // Output-stationary spreading (LDS float atomics are slow on this GPU): each thread owns
@@ -181,7 +160,6 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
 // batches of kOsBatch: their cells, weights and values go to LDS, then for a grid point the
 // contributing nodes of each tile row in reach form a contiguous range of the cell-sorted
 // batch (found from a per-cell start table), so no node outside the window is visited.
-// The box is finally added to the grid with hardware float atomics (boxes overlap).
 constexpr int kOsThreads = 256;
 constexpr int kOsBatch = 256;
 template <int D>
@@ -321,32 +299,11 @@ __global__ void __launch_bounds__(kOsThreads) k_spread_os(SpreadArgs a) {
         }
     }
 
-    R* __restrict__ grid = static_cast<R*>(a.grid);
+    const int ci = xcd_block(int(blockIdx.x), int(gridDim.x));
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
         const int e = tid + k * kOsThreads;
-        if (e >= total) break;
-        if (acc[k].re == R(0) && acc[k].im == R(0)) continue;
-        int rem = e;
-        int64_t gidx = 0;
-        bool ok = true;
-        int64_t st = 1;
-#pragma unroll
-        for (int t = D - 1; t >= 0; --t) {
-            const int ct = rem % W[t];
-            rem /= W[t];
-            int p = n0[t] - m + 1 + ct;
-            if (METHOD == 1) {
-                p = (p % L + L) % L;
-            } else if (p < 0 || p >= L) {
-                ok = false;
-            }
-            gidx += int64_t(p) * st;
-            st *= L;
-        }
-        if (!ok) continue;
-        hbm_add(grid + 2 * gidx, acc[k].re);
-        hbm_add(grid + 2 * gidx + 1, acc[k].im);
+        if (e < total) box_store<R>(a, ci, e, acc[k]);
     }
 }
 
@@ -482,21 +439,11 @@ __global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
     }
 
     if (c1 >= W[1]) return;
-    R* __restrict__ grid = static_cast<R*>(a.grid);
-    int p1 = n0[1] - m + 1 + c1;
-    if (METHOD == 1) p1 = (p1 % L + L) % L;
-    else if (p1 < 0 || p1 >= L) return;
+    const int ci = xcd_block(int(blockIdx.x), int(gridDim.x));
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int c0 = cb + k;
-        if (c0 >= W[0]) break;
-        if (acc[k].re == R(0) && acc[k].im == R(0)) continue;
-        int p0 = n0[0] - m + 1 + c0;
-        if (METHOD == 1) p0 = (p0 % L + L) % L;
-        else if (p0 < 0 || p0 >= L) continue;
-        const int64_t gidx = int64_t(p0) * L + p1;
-        hbm_add(grid + 2 * gidx, acc[k].re);
-        hbm_add(grid + 2 * gidx + 1, acc[k].im);
+        if (c0 < W[0]) box_store<R>(a, ci, c0 * W[1] + c1, acc[k]);
     }
 }
 
@@ -648,23 +595,10 @@ __global__ void __launch_bounds__(256) k_spread_rows3(SpreadArgs a) {
     }
 
     if (c1 >= W[1] || c2 >= W[2]) return;
-    R* __restrict__ grid = static_cast<R*>(a.grid);
-    int p1 = n0[1] - m + 1 + c1, p2 = n0[2] - m + 1 + c2;
-    if (METHOD == 1) {
-        p1 = (p1 % L + L) % L;
-        p2 = (p2 % L + L) % L;
-    } else if (p1 < 0 || p1 >= L || p2 < 0 || p2 >= L) {
-        return;
-    }
+    const int ci = xcd_block(int(blockIdx.x), int(gridDim.x));
     static_for<C>([&](auto c0c) __attribute__((always_inline)) {
         constexpr int c0 = decltype(c0c)::value;
-        if (c0 >= W[0] || (acc[c0].re == R(0) && acc[c0].im == R(0))) return;
-        int p0 = n0[0] - m + 1 + c0;
-        if (METHOD == 1) p0 = (p0 % L + L) % L;
-        else if (p0 < 0 || p0 >= L) return;
-        const int64_t gidx = (int64_t(p0) * L + p1) * L + p2;
-        hbm_add(grid + 2 * gidx, acc[c0].re);
-        hbm_add(grid + 2 * gidx + 1, acc[c0].im);
+        if (c0 < W[0]) box_store<R>(a, ci, (c0 * W[1] + c1) * W[2] + c2, acc[c0]);
     });
 }
 
@@ -937,6 +871,90 @@ KFn grad_d(int d, int m) {
     return nullptr;
 }
 
+// ---------------------------------------------------------------- box merge
+struct MergeArgs {
+    const void* boxes;
+    void* grid;
+    const int32_t* tile_count;   // nodes per tile
+    const int32_t* chunk_off;    // first chunk of each tile
+    int64_t box_vol, n;
+    int L, m, cap;
+    int tile[3], tpd[3], W[3];
+};
+using KFnM = void (*)(MergeArgs);
+
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Calls f(tc, c) for every tile tc (of tpd, edge T) whose box covers grid coordinate p along
+// one dimension, c being p's position in that box: box points n0 - m + 1 + c, c < W, with
+// n0 = tc T, reach p itself (zero-extended sums) or p + s L (periodic sums, boxes wrap).
+template <int METHOD, typename F>
+__device__ __forceinline__ void covering(int p, int L, int T, int tpd, int m, int W, F&& f) {
+    constexpr int s_lo = METHOD == 1 ? -1 : 0, s_hi = METHOD == 1 ? 2 : 0;
+#pragma unroll
+    for (int s = s_lo; s <= s_hi; ++s) {
+        const int q = p + s * L;
+        const int lo = max(0, floor_div(q + m - W + T - 1, T));   // ceil((q + m - W) / T)
+        const int hi = min(tpd - 1, floor_div(q + m - 1, T));
+        for (int tc = lo; tc <= hi; ++tc) f(tc, q + m - 1 - tc * T);
+    }
+}
+
+// One thread per grid point: the sum of the covering boxes' entries, over tiles in row-major
+// order (and s), and over each tile's chunks in order.  Every grid point is written.
+template <typename R, int D, int METHOD>
+__global__ void __launch_bounds__(256) k_box_merge(MergeArgs a) {
+    const int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (gi >= a.n) return;
+    int p[3] = {0, 0, 0};
+    {
+        int64_t r = gi;
+#pragma unroll
+        for (int t = D - 1; t >= 0; --t) {
+            p[t] = int(r % a.L);
+            r /= a.L;
+        }
+    }
+    const Cx<R>* __restrict__ boxes = static_cast<const Cx<R>*>(a.boxes);
+    R re = R(0), im = R(0);
+    auto add_tile = [&](int tile, int e) {
+        const int cnt = a.tile_count[tile];
+        if (cnt == 0) return;
+        const int nch = (cnt + a.cap - 1) / a.cap;
+        const int64_t base = int64_t(a.chunk_off[tile]) * a.box_vol + e;
+        for (int k = 0; k < nch; ++k) {
+            const Cx<R> v = boxes[base + int64_t(k) * a.box_vol];
+            re += v.re;
+            im += v.im;
+        }
+    };
+    if constexpr (D == 1) {
+        covering<METHOD>(p[0], a.L, a.tile[0], a.tpd[0], a.m, a.W[0], [&](int t0, int c0) { add_tile(t0, c0); });
+    } else if constexpr (D == 2) {
+        covering<METHOD>(p[0], a.L, a.tile[0], a.tpd[0], a.m, a.W[0], [&](int t0, int c0) {
+            covering<METHOD>(p[1], a.L, a.tile[1], a.tpd[1], a.m, a.W[1], [&](int t1, int c1) {
+                add_tile(t0 * a.tpd[1] + t1, c0 * a.W[1] + c1);
+            });
+        });
+    } else {
+        covering<METHOD>(p[0], a.L, a.tile[0], a.tpd[0], a.m, a.W[0], [&](int t0, int c0) {
+            covering<METHOD>(p[1], a.L, a.tile[1], a.tpd[1], a.m, a.W[1], [&](int t1, int c1) {
+                covering<METHOD>(p[2], a.L, a.tile[2], a.tpd[2], a.m, a.W[2], [&](int t2, int c2) {
+                    add_tile((t0 * a.tpd[1] + t1) * a.tpd[2] + t2, (c0 * a.W[1] + c1) * a.W[2] + c2);
+                });
+            });
+        });
+    }
+    static_cast<Cx<R>*>(a.grid)[gi] = Cx<R>{re, im};
+}
+
+template <typename R, int METHOD>
+KFnM merge_d(int d) {
+    if (d == 1) return k_box_merge<R, 1, METHOD>;
+    if (d == 2) return k_box_merge<R, 2, METHOD>;
+    return k_box_merge<R, 3, METHOD>;
+}
+
 SpreadArgs make_args(const Plan& p) {
     SpreadArgs a{};
     a.xs = p.d_xs;
@@ -959,18 +977,45 @@ SpreadArgs make_args(const Plan& p) {
 
 }  // namespace
 
-bl_status launch_spread(Plan& p, const void* g, void* grid) {
-    const int64_t n = p.grid_elems();
-    const unsigned zb = unsigned((n + 255) / 256);
-    if (p.prec == BL_F64)
-        hipLaunchKernelGGL(k_zero<double>, dim3(zb), dim3(256), 0, p.stream, static_cast<Cx<double>*>(grid), n);
-    else
-        hipLaunchKernelGGL(k_zero<float>, dim3(zb), dim3(256), 0, p.stream, static_cast<Cx<float>*>(grid), n);
-    BL_HIP(hipGetLastError());
-    if (p.N == 0 || p.nchunks == 0) return BL_OK;
+int64_t spread_box_vol(const Plan& p) {
+    int64_t v = 1;
+    for (int t = 0; t < p.d; ++t) v *= p.tile[t] + 2 * p.m - 1;
+    return v;
+}
+
+size_t spread_boxes_bytes(const Plan& p) {
+    return size_t(std::max<int64_t>(p.nchunks, 1)) * size_t(spread_box_vol(p)) * p.cplx_size();
+}
+
+bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes) {
     SpreadArgs a = make_args(p);
     a.g = g;
     a.grid = grid;
+    a.boxes = boxes;
+    a.box_vol = spread_box_vol(p);
+    MergeArgs ma{};
+    ma.boxes = boxes;
+    ma.grid = grid;
+    ma.tile_count = p.d_tile_count;
+    ma.chunk_off = p.d_chunk_offset;
+    ma.box_vol = a.box_vol;
+    ma.n = p.grid_elems();
+    ma.L = int(p.L);
+    ma.m = p.m;
+    ma.cap = p.chunk_cap;
+    for (int t = 0; t < 3; ++t) {
+        ma.tile[t] = p.tile[t];
+        ma.tpd[t] = p.tiles_per_dim[t];
+        ma.W[t] = p.tile[t] + 2 * p.m - 1;
+    }
+    auto merge = [&]() -> bl_status {
+        const KFnM mf = p.prec == BL_F64 ? (p.method == BL_NFFT ? merge_d<double, 1>(p.d) : merge_d<double, 0>(p.d))
+                                         : (p.method == BL_NFFT ? merge_d<float, 1>(p.d) : merge_d<float, 0>(p.d));
+        hipLaunchKernelGGL(mf, dim3(unsigned((ma.n + 255) / 256)), dim3(256), 0, p.stream, ma);
+        BL_HIP(hipGetLastError());
+        return BL_OK;
+    };
+    if (p.N == 0 || p.nchunks == 0) return merge();   // every tile empty: zeros
     // Row kernels (d = 2: box edges <= 32; d = 3: <= 16); otherwise the output-stationary
     // kernel when the box fits its points per thread and its LDS fits; otherwise the
     // LDS-atomic kernel.  BL_SPREAD_OS / BL_SPREAD_ATOMIC force the latter two.
@@ -987,7 +1032,7 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
     const bool use_rows = by_rows && p.d == 2 && p.tile[0] + 2 * p.m - 1 <= 32 && p.tile[1] + 2 * p.m - 1 <= 32;
     bool use_rows3 = by_rows && p.d == 3 && p.m <= 7;
     for (int t = 0; t < 3 && use_rows3; ++t) use_rows3 = p.tile[t] + 2 * p.m - 1 <= kRows3Box;
-    const bool use_os = !use_rows && !use_rows3 && box <= int64_t(kp) * kOsThreads && os_lds <= 64 * 1024 &&
+    const bool use_os = !use_rows && !use_rows3 && box <= int64_t(kp) * kOsThreads && os_lds <= 160 * 1024 &&
                         std::getenv("BL_SPREAD_ATOMIC") == nullptr;
     KFn fn;
     // Double row kernels with closed-form weights are separate instantiations, so that the
@@ -1019,7 +1064,7 @@ bl_status launch_spread(Plan& p, const void* g, void* grid) {
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);
     BL_HIP(hipGetLastError());
-    return BL_OK;
+    return merge();
 }
 
 bl_status launch_grad_x(Plan& p, const void* g, void* gx) {

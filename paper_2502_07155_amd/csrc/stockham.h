@@ -21,6 +21,14 @@ template <typename R>
 __device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
+// v * w in the precision of w (double twiddles: the product is formed in double and rounded
+// once to R).
+template <typename R, typename TW>
+__device__ __forceinline__ Cx<R> mulw(Cx<R> v, Cx<TW> w) {
+    const TW re = TW(v.re) * w.re - TW(v.im) * w.im;
+    const TW im = TW(v.re) * w.im + TW(v.im) * w.re;
+    return {R(re), R(im)};
+}
 // a * (dir * i)
 template <typename R, int DIR>
 __device__ __forceinline__ Cx<R> rot(Cx<R> a) {

@@ -35,8 +35,9 @@ def window_transform(v, M: int, L: int, m: int, beta: float = 0.0, window: str =
 class Plan:
     """One transform configuration (Algorithm 4.2 or Algorithm 2.1) on one device/stream.
 
-    precision: "f64", "f32" or "f32c" (float data, FP64 FFT arithmetic and FP64
-    accumulation of the short sums).
+    precision: "f64", "f32" (plain float), "f32c" (float data and FFT arithmetic with FP64
+    twiddles and deconvolution factors, two-sum compensated short sums) or "f32d" (float
+    data, FP64 FFT arithmetic and FP64 accumulation of the short sums).
     Inputs/outputs are torch tensors on the plan's device: fhat (M,)*d complex, nodes (N, d)
     real, f (N,) complex, in the plan's precision."""
 
@@ -113,6 +114,13 @@ class Plan:
         self._forward_version += 1
         return out
 
+    def samples(self, fhat: torch.Tensor) -> None:
+        """bl_samples: steps 1-2 alone; the samples theta stay in the plan (theta())."""
+        self._check(fhat, (self.M,) * self.d, self.complex_dtype, "fhat")
+        with self._dev():
+            check(self._lib.bl_samples(self.handle, _ptr(fhat)), "bl_samples")
+        self._forward_version += 1
+
     def state(self) -> tuple:
         """(node binding, forward) counters: identifies the samples theta the plan holds."""
         return (self._nodes_version, self._forward_version)
@@ -162,7 +170,10 @@ class Plan:
         check(self._lib.bl_plan_stats(self.handle, ctypes.byref(s)), "bl_plan_stats")
         return {"n_nodes": s.n_nodes, "n_outside": s.n_outside, "n_chunks": s.n_chunks,
                 "tile": tuple(s.tile), "chunk_cap": s.chunk_cap,
-                "workspace_bytes": s.workspace_bytes, "beta": s.beta}
+                "workspace_bytes": s.workspace_bytes, "beta": s.beta,
+                "weight_fit_err": s.weight_fit_err,
+                "fft_lines": (tuple(s.fft_lines[0:3]), tuple(s.fft_lines[3:6])),
+                "tuned": {"fft": int(s.tuned[0]), "tiles": int(s.tuned[1])}}
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:

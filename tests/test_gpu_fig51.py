@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import workloads as W
 
 pytestmark = pytest.mark.gpu
 
@@ -78,17 +79,17 @@ def test_figure_5_1_on_the_gpu():
     assert nfs[inband].max() < sh[inband].max() / 100             # standard beta: (5.1) is better
 
 
-def test_interpolate_with_non_power_of_two_L_and_forward_refused():
+def test_forward_and_adjoint_at_the_figures_L():
+    """L = 40 (not a power of two) runs steps 1-2 by the chirp-z passes: forward and adjoint
+    of an FP64 plan against the oracle."""
     import torch
     from paper_2502_07155_amd import Plan
-    from paper_2502_07155_amd._lib import BLNFFTError
     M, L, m = 20, 40, 5
+    p = W.custom_problem(1, M, L, m, 300, seed=41, with_targets=True)
     plan = Plan(1, M, L, m, precision="f64")
-    plan.set_nodes(torch.zeros((3, 1), dtype=torch.float64, device="cuda"))
-    with pytest.raises(BLNFFTError) as e:
-        plan.forward(torch.zeros(M, dtype=torch.complex128, device="cuda"))
-    assert e.value.status == 6
-    with pytest.raises(BLNFFTError) as e:
-        plan.adjoint(torch.zeros(3, dtype=torch.complex128, device="cuda"))
-    assert e.value.status == 6
+    plan.set_nodes(torch.from_numpy(p.x).cuda())
+    f = plan.forward(torch.from_numpy(p.fhat).cuda()).cpu().numpy()
+    assert O.rel_err_inf(f, O.forward_shannon(p.fhat, p.x, L, m)) <= 1e-12
+    a = plan.adjoint(torch.from_numpy(p.y).cuda()).cpu().numpy()
+    assert O.rel_err_inf(a, O.adjoint_shannon(p.y, p.x, M, L, m)) <= 1e-12
     plan.close()
