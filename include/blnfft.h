@@ -180,6 +180,20 @@ bl_status bl_get_theta(bl_plan plan, void* theta_dev);
  * Asynchronous.  The same L restrictions as bl_forward. */
 bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev);
 
+/* bl_adjoint for callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same computation and
+ * kernels, with the spreading grid and the work chunks' boxes held in a fixed device
+ * scratch array of the library (64 MiB per GPU, held until the process ends) instead of
+ * plan memory that bl_adjoint allocates on its first call.  Allocates nothing (the plan's
+ * own FFT buffers, allocated by bl_plan_create, are used as by bl_adjoint).
+ *   g_dev : N complex (input).   fhat_dev : M^d complex (output, overwritten).
+ * BL_EUNSUPPORTED when the grid (L^d complex values of the plan's type) and the boxes (one
+ * prod_t (tile_t + 2m - 1) complex values per work chunk, bl_plan_stats) exceed 64 MiB
+ * (e.g. d = 3, L = 256).  All calls on one GPU share the one array and each leaves its
+ * contents behind, so calls that overlap in time on one GPU (other streams or threads)
+ * race; order them on one stream.  Asynchronous. */
+bl_status bl_adjoint_noalloc(bl_plan plan, const void* g_dev, void* fhat_dev);
+
 /* Gradient with respect to the nodes: gx[j*d + t] = Re( conj(g_j) * d f_j / d x_jt ),
  * f from the last bl_forward (BL_SHANNON only).  f_j is the short sum (4.8) over the
  * samples theta of step 2 (the factorisation (4.11) with Psi's entries psi(x_j - l/L)),

@@ -20,7 +20,7 @@ EXPORTS = [
     "bl_plan_create", "bl_set_nodes", "bl_precompute_weights", "bl_forward", "bl_samples",
     "bl_interpolate",
     "bl_get_theta",
-    "bl_adjoint", "bl_grad_x", "bl_plan_stats", "bl_plan_destroy", "bl_window_transform",
+    "bl_adjoint", "bl_adjoint_noalloc", "bl_grad_x", "bl_plan_stats", "bl_plan_destroy", "bl_window_transform",
     "bl_batch_create", "bl_batch_set_nodes", "bl_batch_forward", "bl_batch_destroy",
     "bl_status_string", "bl_last_error", "bl_version",
 ]
@@ -70,6 +70,7 @@ def load() -> ctypes.CDLL:
         "bl_interpolate": [vp, vp, vp],
         "bl_get_theta": [vp, vp],
         "bl_adjoint": [vp, vp, vp],
+        "bl_adjoint_noalloc": [vp, vp, vp],
         "bl_grad_x": [vp, vp, vp],
         "bl_plan_stats": [vp, P(Stats)],
         "bl_plan_destroy": [vp],

@@ -702,6 +702,15 @@ bl_status bl_adjoint(bl_plan plan, const void* g_dev, void* fhat_dev) {
     return launch_adjoint_fft(p, p.d_sgrid, fhat_dev);
 }
 
+bl_status bl_adjoint_noalloc(bl_plan plan, const void* g_dev, void* fhat_dev) {
+    BL_TRY(check_plan(plan));
+    Plan& p = plan->p;
+    if (!p.fft_ok) return fail(BL_EUNSUPPORTED, "bl_adjoint_noalloc: L + M - 1 above the chirp-z LDS size for d >= 2");
+    if (!p.have_nodes) return fail(BL_ESTATE, "bl_set_nodes must succeed before bl_adjoint_noalloc");
+    if (!fhat_dev || (p.N > 0 && !g_dev)) return fail(BL_EINVAL, "NULL buffer");
+    return launch_adjoint_noalloc(p, g_dev, fhat_dev);
+}
+
 bl_status bl_grad_x(bl_plan plan, const void* g_dev, void* gx_dev) {
     BL_TRY(check_plan(plan));
     Plan& p = plan->p;

@@ -263,6 +263,10 @@ bl_status launch_binning(Plan& p, const void* x, int64_t N);
 // per-chunk boxes into `boxes` (spread_boxes_bytes), then their fixed-order merge.
 bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes);
 size_t spread_boxes_bytes(const Plan& p);
+// bl_adjoint with the spreading grid and chunk boxes in the library's fixed device scratch
+// (no allocation); BL_EUNSUPPORTED when they exceed it.
+bl_status launch_adjoint_noalloc(Plan& p, const void* g, void* fhat_out);
+size_t noalloc_scratch_bytes();
 // One chirp-z pass (czt.hip): lines outer x inner, Min inputs and Mout outputs per line in
 // centred order; dir +1 forward (band -> grid), -1 adjoint (grid -> band).
 bl_status launch_czt_pass(Plan& p, int dir, const void* in, void* out, int outer, int inner, int Min,

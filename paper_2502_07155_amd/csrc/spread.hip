@@ -13,6 +13,7 @@
 // The gradient kernel mirrors the short-sum kernel, with psi' in one dimension:
 //   d f_j / d x_jt = L sum_l theta_l psi_g'(u_t) prod_{s != t} psi_g(u_s).
 #include <cstdlib>
+#include <mutex>
 #include <string>
 
 #include "blnfft_internal.h"
@@ -1065,6 +1066,63 @@ bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes) {
     hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);
     BL_HIP(hipGetLastError());
     return merge();
+}
+
+// ---------------------------------------------------------------- allocation-free adjoint
+// Spreading target of bl_adjoint_noalloc: a file-scope device array instead of plan memory,
+// for callers that cannot allocate (code under stream capture, serving loops).  Every GPU
+// the library runs on holds one copy until the process ends; all calls on one GPU share it,
+// so such calls that overlap in time on one GPU race.  In host code `scratch` is only a
+// stand-in for the symbol: its device address comes from hipGetSymbolAddress, looked up
+// once per device with that device current, and only that address is passed to kernels.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+constexpr int kNoallocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoallocMaxDevices] = {};
+
+// Device address of `scratch` on the current device (which must be `device`).
+bl_status scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kNoallocMaxDevices) {
+        set_error("device index above the allocation-free entry point's table");
+        return BL_EUNSUPPORTED;
+    }
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return BL_EDEVICE;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return BL_OK;
+}
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return kNoallocScratchBytes; }
+
+bl_status launch_adjoint_noalloc(Plan& p, const void* g, void* fhat_out) {
+    const size_t grid_bytes = (size_t(p.grid_elems()) * p.cplx_size() + 255) & ~size_t(255);
+    const size_t need = grid_bytes + spread_boxes_bytes(p);
+    if (need > kNoallocScratchBytes) {
+        set_error("bl_adjoint_noalloc: the spreading grid and chunk boxes (" + std::to_string(need) +
+                  " bytes) exceed its fixed device scratch of " + std::to_string(kNoallocScratchBytes) +
+                  " bytes; use bl_adjoint");
+        return BL_EUNSUPPORTED;
+    }
+    void* base = nullptr;
+    BL_TRY(scratch_address(p.device, &base));
+    // grid first, then the chunk boxes; every box entry and every grid point is written
+    // before it is read, so the array's contents from an earlier call never show
+    void* grid = base;
+    void* boxes = static_cast<unsigned char*>(base) + grid_bytes;
+    BL_TRY(launch_spread(p, g, grid, boxes));
+    return launch_adjoint_fft(p, grid, fhat_out);
 }
 
 bl_status launch_grad_x(Plan& p, const void* g, void* gx) {

@@ -156,6 +156,15 @@ class Plan:
             check(self._lib.bl_adjoint(self.handle, _ptr(g), _ptr(out)), "bl_adjoint")
         return out
 
+    def adjoint_noalloc(self, g: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """bl_adjoint_noalloc: the adjoint without any device allocation (the caller passes
+        the output; the spreading grid lives in the library's fixed device scratch)."""
+        self._check(g, (self.N,), self.complex_dtype, "g")
+        self._check(out, (self.M,) * self.d, self.complex_dtype, "out")
+        with self._dev():
+            check(self._lib.bl_adjoint_noalloc(self.handle, _ptr(g), _ptr(out)), "bl_adjoint_noalloc")
+        return out
+
     def grad_x(self, g: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         self._check(g, (self.N,), self.complex_dtype, "g")
         if out is None:
