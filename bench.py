@@ -256,11 +256,25 @@ def leg_nfft(steps, warmup, f_shannon, p_shannon, checks: list):
     return out
 
 
+def plan_shape(plan) -> dict:
+    """Launch shapes the plan runs with (tile edge, chunk capacity, FFT lines per workgroup)
+    and how they were chosen (0 built-in rule, 1 timed, 2 tuning cache)."""
+    st = plan.stats()
+    return {"tile": st["tile"][:plan.d], "chunk_cap": st["chunk_cap"], "chunks": st["n_chunks"],
+            "fft_lines_forward": st["fft_lines"][0][:plan.d], "fft_lines_adjoint": st["fft_lines"][1][:plan.d],
+            "fft_radix_forward": st["fft_radix"][0][:plan.d], "fft_radix_adjoint": st["fft_radix"][1][:plan.d],
+            "tuned": st["tuned"]}
+
+
 def leg_plan(name, prec, steps, warmup, checks: list, sample=5000):
     p, plan, f, ms, gms, plan_ms = run_plan(name, prec, steps, warmup)
+    shape = plan_shape(plan)
     plan.close()
-    rec = {"value": p.N / (ms * 1e-3), "ms_per_step": ms, "gather_ms": gms, "plan_ms": plan_ms,
-           "precision": prec}
+    ab = algorithmic_bytes(p.d, p.M, p.L, p.N, 16 if prec == "f64" else 8, 8 if prec == "f64" else 4)
+    rec = {"value": p.N / (ms * 1e-3), "ms_per_step": ms, "gather_ms": gms, "fft_ms": plan.fft_ms,
+           "fft_GBs": ab["fft"] / (plan.fft_ms * 1e-3) / 1e9,
+           "fft_frac_of_hbm_peak": ab["fft"] / (plan.fft_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "plan_ms": plan_ms, "precision": prec, "shape": shape}
     checks.append(accuracy_check(rec, p, f, sample))
     return rec
 
@@ -852,6 +866,7 @@ def main():
         plan.set_nodes(xr)
     torch.cuda.synchronize()
     rec["rebind_ms"] = (time.perf_counter() - t0) * 1e3 / 5
+    rec["shape"] = plan_shape(plan)
     plan.close()
     checks.append(accuracy_check(rec, p, f, key="rel_err", l2=True))
     if not args.headline_only and args.workload == HEADLINE and prec != "f64":

@@ -88,6 +88,8 @@ typedef struct {
                                  weight (0 when FP64 plans evaluate them exactly)          */
     int64_t fft_lines[2][3];  /* lines per workgroup of the forward [0] and adjoint [1]
                                  transform pass over each axis (0: the built-in rule)      */
+    int64_t fft_radix[2][3];  /* values per thread (radix, 4 or 16) of the same passes
+                                 (0: the built-in rule; chirp-z passes use 16)             */
     int64_t tuned[2];         /* how the FFT lines [0] and the tile edge and chunk
                                  capacity [1] were chosen: 0 built-in rule or environment
                                  override, 1 timed by this plan, 2 from the tuning cache   */

@@ -43,6 +43,7 @@ class Stats(ctypes.Structure):
         ("beta", ctypes.c_double),
         ("weight_fit_err", ctypes.c_double),
         ("fft_lines", ctypes.c_int64 * 6),
+        ("fft_radix", ctypes.c_int64 * 6),
         ("tuned", ctypes.c_int64 * 2),
     ]
 

@@ -109,6 +109,8 @@ void free_plan(Plan& p) {
     hipFree(p.d_tile_offset);
     hipFree(p.d_tile_cursor);
     hipFree(p.d_chunk_offset);
+    hipFree(p.d_scan);
+    p.d_scan = nullptr;
     hipFree(p.d_flags);
     hipFree(p.d_wpre);
     p.d_wpre = nullptr;
@@ -183,11 +185,14 @@ bl_status apply_tiles(Plan& p, int T, int cap) {
         hipFree(*a);
         *a = nullptr;
     }
-    p.workspace_bytes -= size_t(p.tile_alloc) * 4 * sizeof(int32_t);
+    hipFree(p.d_scan);
+    p.d_scan = nullptr;
+    p.workspace_bytes -= size_t(p.tile_alloc) * 4 * sizeof(int32_t) + (p.tile_alloc ? tile_scan_scratch_bytes(p.tile_alloc) : 0);
     p.tile_alloc = 0;
     size_t extra = 0;
     for (int32_t** a : {&p.d_tile_count, &p.d_tile_offset, &p.d_tile_cursor, &p.d_chunk_offset})
         BL_TRY(dev_alloc(a, sizeof(int32_t) * size_t(p.ntiles), &extra));
+    BL_TRY(dev_alloc(reinterpret_cast<char**>(&p.d_scan), tile_scan_scratch_bytes(p.ntiles), &extra));
     p.tile_alloc = p.ntiles;
     p.workspace_bytes += extra;
     return BL_OK;
@@ -735,7 +740,10 @@ bl_status bl_plan_stats(bl_plan plan, bl_stats* out) {
     out->beta = p.beta;
     out->weight_fit_err = p.prec == BL_F64 ? (p.use_poly64 ? p.poly64_err : 0.0) : p.poly_err;
     for (int i = 0; i < 2; ++i)
-        for (int t = 0; t < 3; ++t) out->fft_lines[i][t] = p.fft_lines[i][t];
+        for (int t = 0; t < 3; ++t) {
+            out->fft_lines[i][t] = p.fft_lines[i][t];
+            out->fft_radix[i][t] = p.fft_radix[i][t];
+        }
     out->tuned[0] = p.tune_fft_source;
     out->tuned[1] = p.tune_tile_source;
     return BL_OK;

@@ -1,8 +1,9 @@
 // Autotuner of the per-plan launch shapes, with a persistent cache.
 //
 // Measured on the plan's own device and stream, never guessed:
-//  * FFT passes (at plan creation): lines per workgroup of every forward and adjoint pass,
-//    1, 2, ..., 16, timed with HIP events on scratch buffers (tune_fft_lines, fft.hip);
+//  * FFT passes (at plan creation): lines per workgroup (1, 2, ..., 64, as far as the
+//    pass's LDS and thread limits allow) and values per thread (4 or 16) of every forward
+//    and adjoint pass, timed with HIP events on scratch buffers (tune_fft_lines, fft.hip);
 //  * short sums (at the first node binding with at least kTuneMinNodes nodes): the tile
 //    edge of the node binning and the work-chunk capacity, timed by binning the nodes with
 //    each candidate and running the short-sum kernel on zero samples.
@@ -156,8 +157,11 @@ bl_status autotune_fft(Plan& p) {
     if (!p.fft_ok || !tuning_enabled() || std::getenv("BL_FFT_LINES") || std::getenv("BL_CZT_LINES")) return BL_OK;
     const std::string key = plan_key(p, "fft");
     std::vector<int> v;
-    if (lookup(key, &v) && v.size() == 6) {
-        for (int i = 0; i < 6; ++i) p.fft_lines[i / 3][i % 3] = v[i];
+    if (lookup(key, &v) && v.size() == 12) {
+        for (int i = 0; i < 6; ++i) {
+            p.fft_lines[i / 3][i % 3] = v[i];
+            p.fft_radix[i / 3][i % 3] = v[6 + i];
+        }
         p.tune_fft_source = 2;
         return BL_OK;
     }
@@ -176,13 +180,15 @@ bl_status autotune_fft(Plan& p) {
     hipFree(a);
     hipFree(b);
     if (st != BL_OK) {
-        for (auto& row : p.fft_lines)
-            for (int& x : row) x = 0;
+        for (int i = 0; i < 6; ++i) p.fft_lines[i / 3][i % 3] = p.fft_radix[i / 3][i % 3] = 0;
         set_error("");
         return BL_OK;
     }
-    v.assign(6, 0);
-    for (int i = 0; i < 6; ++i) v[i] = p.fft_lines[i / 3][i % 3];
+    v.assign(12, 0);
+    for (int i = 0; i < 6; ++i) {
+        v[i] = p.fft_lines[i / 3][i % 3];
+        v[6 + i] = p.fft_radix[i / 3][i % 3];
+    }
     store(key, v);
     p.tune_fft_source = 1;
     return BL_OK;

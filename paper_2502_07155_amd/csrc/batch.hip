@@ -359,24 +359,15 @@ __device__ __forceinline__ int find_instance(const long long* off, int count, lo
     return lo;
 }
 
-// Nodes of one workgroup are consecutive, so they fall into few tiles of one or two
-// instances: counts are aggregated in an LDS histogram over the workgroup's tile range
-// [tmin, tmin + kBinSpan) and flushed with one global atomic per tile; tiles beyond that
-// range (rare) use global atomics directly.
+// Binning with per-workgroup LDS histograms (as for single transforms): a workgroup takes
+// kBinPer * kBinThreads consecutive nodes, which fall into the tiles of few instances,
+// and walks the tiles between its smallest and largest in windows of kLdsBins, counting
+// its nodes of the window in LDS and adding each nonzero count to the global counter once.
+// The scatter recounts window by window, keeps each node's LDS rank, reserves one range
+// per tile with a single global atomic and places every node at its rank in that range.
 constexpr int kBinThreads = 256;
-constexpr int kBinSpan = 512;
-
-__device__ __forceinline__ int block_min(int v, int* red) {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = kBinThreads / 2; off > 0; off >>= 1) {
-        if (int(threadIdx.x) < off) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + off]);
-        __syncthreads();
-    }
-    const int r = red[0];
-    __syncthreads();
-    return r;
-}
+constexpr int kBinPer = 16;
+constexpr int kLdsBins = 8192;
 
 __device__ __forceinline__ int node_tile_of(const BBinArgs& a, long long j, unsigned& invalid, unsigned& outside) {
     const int i = find_instance(a.node_off, a.count, j);
@@ -394,57 +385,117 @@ __device__ __forceinline__ int node_tile_of(const BBinArgs& a, long long j, unsi
     return d.tile_base + (n + d.L / 2) / a.tile;
 }
 
-__global__ void __launch_bounds__(kBinThreads) k_bbin_count(BBinArgs a) {
-    __shared__ int hist[kBinSpan];
-    __shared__ int red[kBinThreads];
-    __shared__ unsigned flag_cnt[2];
-    const long long j = (long long)blockIdx.x * kBinThreads + threadIdx.x;
-    for (int e = threadIdx.x; e < kBinSpan; e += kBinThreads) hist[e] = 0;
-    if (threadIdx.x < 2) flag_cnt[threadIdx.x] = 0u;
-    unsigned invalid = 0, outside = 0;
-    int tile = 0x7fffffff;
-    if (j < a.N) {
-        tile = node_tile_of(a, j, invalid, outside);
-        a.node_tile[j] = tile;
+// Smallest and largest tile among the workgroup's nodes (tl < 0: none), uniform over the
+// workgroup; hi < lo when it has no nodes.
+__device__ __forceinline__ void tile_range(const int* tl, int& lo, int& hi) {
+    __shared__ int s_lo, s_hi;
+    if (threadIdx.x == 0) {
+        s_lo = 0x7fffffff;
+        s_hi = -1;
     }
-    const int tmin = block_min(tile, red);   // also orders the LDS clears before use
-    if (j < a.N) {
-        const int k = tile - tmin;
-        if (k < kBinSpan) atomicAdd(&hist[k], 1);
-        else atomicAdd(&a.tile_count[tile], 1);
+    int a = 0x7fffffff, b = -1;
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k) {
+        if (tl[k] >= 0) {
+            a = min(a, tl[k]);
+            b = max(b, tl[k]);
+        }
     }
-    if (invalid) atomicAdd(&flag_cnt[0], invalid);
-    if (outside) atomicAdd(&flag_cnt[1], outside);
+    for (int off = 32; off > 0; off >>= 1) {
+        a = min(a, __shfl_xor(a, off));
+        b = max(b, __shfl_xor(b, off));
+    }
     __syncthreads();
-    for (int e = threadIdx.x; e < kBinSpan; e += kBinThreads)
-        if (hist[e]) atomicAdd(&a.tile_count[tmin + e], hist[e]);
-    if (threadIdx.x < 2 && flag_cnt[threadIdx.x])
-        atomicAdd(&a.flags[threadIdx.x], (unsigned long long)flag_cnt[threadIdx.x]);
+    if ((threadIdx.x & 63) == 0 && b >= 0) {
+        atomicMin(&s_lo, a);
+        atomicMax(&s_hi, b);
+    }
+    __syncthreads();
+    lo = s_lo;
+    hi = s_hi;
 }
 
-// Each node takes its rank within the workgroup's share of its tile from the LDS
-// histogram; the workgroup reserves each tile's share with one global atomic.
+__global__ void __launch_bounds__(kBinThreads) k_bbin_count(BBinArgs a, int ntiles) {
+    __shared__ int hist[kLdsBins];
+    const long long j0 = (long long)blockIdx.x * (kBinThreads * kBinPer) + threadIdx.x;
+    int tl[kBinPer];
+    unsigned invalid = 0, outside = 0;
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k) {
+        const long long j = j0 + (long long)k * kBinThreads;
+        tl[k] = -1;
+        if (j < a.N) {
+            tl[k] = node_tile_of(a, j, invalid, outside);
+            a.node_tile[j] = tl[k];
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        invalid += __shfl_xor(invalid, off);
+        outside += __shfl_xor(outside, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (invalid) atomicAdd(&a.flags[0], (unsigned long long)invalid);
+        if (outside) atomicAdd(&a.flags[1], (unsigned long long)outside);
+    }
+    int tlo, thi;
+    tile_range(tl, tlo, thi);
+    for (int w0 = thi < 0 ? ntiles : (tlo / kLdsBins) * kLdsBins; w0 <= thi && w0 < ntiles; w0 += kLdsBins) {
+        const int nw = min(kLdsBins, ntiles - w0);
+        __syncthreads();   // previous window flushed
+        for (int e = threadIdx.x; e < nw; e += kBinThreads) hist[e] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kBinPer; ++k) {
+            const int e = tl[k] - w0;
+            if (tl[k] >= 0 && e >= 0 && e < nw) atomicAdd(&hist[e], 1);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nw; e += kBinThreads)
+            if (hist[e]) atomicAdd(&a.tile_count[w0 + e], hist[e]);
+    }
+}
+
 __global__ void __launch_bounds__(kBinThreads) k_bbin_scatter(const float* __restrict__ x, long long N,
                                                              const int32_t* node_tile, const int32_t* offset,
                                                              int32_t* cursor, int32_t* perm,
-                                                             float* __restrict__ xs) {
-    __shared__ int hist[kBinSpan];
-    __shared__ int red[kBinThreads];
-    const long long j = (long long)blockIdx.x * kBinThreads + threadIdx.x;
-    for (int e = threadIdx.x; e < kBinSpan; e += kBinThreads) hist[e] = 0;
-    const int tile = j < N ? node_tile[j] : 0x7fffffff;
-    const int tmin = block_min(tile, red);
-    int rank = -1;
-    if (j < N && tile - tmin < kBinSpan) rank = atomicAdd(&hist[tile - tmin], 1);
-    __syncthreads();
-    for (int e = threadIdx.x; e < kBinSpan; e += kBinThreads)
-        if (hist[e]) hist[e] = atomicAdd(&cursor[tmin + e], hist[e]);
-    __syncthreads();
-    if (j >= N) return;
-    const int pos = rank >= 0 ? offset[tile] + hist[tile - tmin] + rank
-                              : offset[tile] + atomicAdd(&cursor[tile], 1);
-    perm[pos] = int32_t(j);
-    xs[pos] = x[j];
+                                                             float* __restrict__ xs, int ntiles) {
+    __shared__ int hist[kLdsBins];   // counts, then the start of this workgroup's range
+    const long long j0 = (long long)blockIdx.x * (kBinThreads * kBinPer) + threadIdx.x;
+    int tl[kBinPer], rank[kBinPer];
+#pragma unroll
+    for (int k = 0; k < kBinPer; ++k) {
+        const long long j = j0 + (long long)k * kBinThreads;
+        tl[k] = j < N ? node_tile[j] : -1;
+        rank[k] = 0;
+    }
+    int tlo, thi;
+    tile_range(tl, tlo, thi);
+    for (int w0 = thi < 0 ? ntiles : (tlo / kLdsBins) * kLdsBins; w0 <= thi && w0 < ntiles; w0 += kLdsBins) {
+        const int nw = min(kLdsBins, ntiles - w0);
+        __syncthreads();   // previous window placed
+        for (int e = threadIdx.x; e < nw; e += kBinThreads) hist[e] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kBinPer; ++k) {
+            const int e = tl[k] - w0;
+            if (tl[k] >= 0 && e >= 0 && e < nw) rank[k] = atomicAdd(&hist[e], 1);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nw; e += kBinThreads) {
+            const int c = hist[e];
+            if (c) hist[e] = offset[w0 + e] + atomicAdd(&cursor[w0 + e], c);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kBinPer; ++k) {
+            const int e = tl[k] - w0;
+            if (tl[k] < 0 || e < 0 || e >= nw) continue;
+            const long long j = j0 + (long long)k * kBinThreads;
+            const int pos = hist[e] + rank[k];
+            perm[pos] = int32_t(j);
+            xs[pos] = x[j];
+        }
+    }
 }
 
 // Chunk list entry: {tile, start, count, instance}.
@@ -572,38 +623,6 @@ __device__ __forceinline__ void batch_gather_chunk(const BGatherArgs& a, const i
                          });
 }
 
-__global__ void k_tile_scan_b(const int32_t* count, int32_t* offset, int32_t* chunk_off,
-                              long long ntiles, int cap, unsigned long long* flags) {
-    __shared__ long long s1[1024];
-    __shared__ long long s2[1024];
-    const int tid = threadIdx.x, NT = blockDim.x;
-    const long long per = (ntiles + NT - 1) / NT;
-    const long long beg = tid * per, end = beg + per < ntiles ? beg + per : ntiles;
-    long long x = 0, y = 0;
-    for (long long i = beg; i < end; ++i) {
-        x += count[i];
-        y += (count[i] + cap - 1) / cap;
-    }
-    s1[tid] = x;
-    s2[tid] = y;
-    __syncthreads();
-    for (int off = 1; off < NT; off *= 2) {
-        const long long va = tid >= off ? s1[tid - off] : 0, vb = tid >= off ? s2[tid - off] : 0;
-        __syncthreads();
-        s1[tid] += va;
-        s2[tid] += vb;
-        __syncthreads();
-    }
-    long long ea = s1[tid] - x, eb = s2[tid] - y;
-    for (long long i = beg; i < end; ++i) {
-        offset[i] = int32_t(ea);
-        chunk_off[i] = int32_t(eb);
-        ea += count[i];
-        eb += (count[i] + cap - 1) / cap;
-    }
-    if (tid == NT - 1) flags[2] = (unsigned long long)s2[NT - 1];
-}
-
 // ---------------------------------------------------------------- host helpers
 int ilog2i(int64_t v) {
     int l = 0;
@@ -652,6 +671,7 @@ struct bl_batch_s {
     int32_t* d_tile_cursor = nullptr;
     int32_t* d_chunk_offset = nullptr;
     int32_t* d_tile_inst = nullptr;
+    void* d_scan = nullptr;   // block sums of the tile scans
     int4* d_chunks = nullptr;
     unsigned long long* d_flags = nullptr;
     int64_t ntiles = 0, chunk_alloc = 0, nchunks = 0, tile_alloc = 0;
@@ -692,7 +712,7 @@ void free_batch(bl_batch_s* b) {
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     void* ptrs[] = {b->d_desc, b->d_node_off, b->d_pre, b->d_post, b->d_h, b->d_tw, b->d_theta,
                     b->d_scratch, b->d_coef, b->d_items, b->d_dif, b->d_comb, b->d_xs, b->d_perm, b->d_node_tile, b->d_tile_count,
-                    b->d_tile_offset, b->d_tile_cursor, b->d_chunk_offset, b->d_tile_inst,
+                    b->d_tile_offset, b->d_tile_cursor, b->d_chunk_offset, b->d_tile_inst, b->d_scan,
                     b->d_chunks, b->d_flags};
     for (void* q : ptrs) (void)hipFree(q);
 }
@@ -790,13 +810,16 @@ bl_status batch_bin(bl_batch_s* b, const float* x, int tile) {
         (void)hipFree(b->d_tile_cursor);
         (void)hipFree(b->d_chunk_offset);
         (void)hipFree(b->d_tile_inst);
+        (void)hipFree(b->d_scan);
         b->d_tile_count = b->d_tile_offset = b->d_tile_cursor = b->d_chunk_offset = b->d_tile_inst = nullptr;
+        b->d_scan = nullptr;
         b->tile_alloc = 0;
         BL_TRY(balloc(&b->d_tile_count, sizeof(int32_t) * nt));
         BL_TRY(balloc(&b->d_tile_offset, sizeof(int32_t) * nt));
         BL_TRY(balloc(&b->d_tile_cursor, sizeof(int32_t) * nt));
         BL_TRY(balloc(&b->d_chunk_offset, sizeof(int32_t) * nt));
         BL_TRY(balloc(&b->d_tile_inst, sizeof(int32_t) * nt));
+        BL_TRY(balloc(reinterpret_cast<char**>(&b->d_scan), tile_scan_scratch_bytes(nt)));
         b->tile_alloc = nt;
     }
     if (chunk_bound > b->chunk_alloc) {
@@ -812,7 +835,7 @@ bl_status batch_bin(bl_batch_s* b, const float* x, int tile) {
     BL_HIP(hipMemsetAsync(b->d_tile_count, 0, sizeof(int32_t) * nt, s));
     BL_HIP(hipMemsetAsync(b->d_tile_cursor, 0, sizeof(int32_t) * nt, s));
     BL_HIP(hipMemsetAsync(b->d_flags, 0, sizeof(unsigned long long) * 4, s));
-    const unsigned nb = unsigned((N + 255) / 256);
+    const unsigned nb = unsigned((N + kBinThreads * kBinPer - 1) / (kBinThreads * kBinPer));
     if (N > 0) {
         BBinArgs ba{};
         ba.x = x;
@@ -824,15 +847,14 @@ bl_status batch_bin(bl_batch_s* b, const float* x, int tile) {
         ba.node_tile = b->d_node_tile;
         ba.tile_count = b->d_tile_count;
         ba.flags = b->d_flags;
-        hipLaunchKernelGGL(k_bbin_count, dim3(nb), dim3(kBinThreads), 0, s, ba);
+        hipLaunchKernelGGL(k_bbin_count, dim3(nb), dim3(kBinThreads), 0, s, ba, int(nt));
         BL_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_tile_scan_b, dim3(1), dim3(1024), 0, s, b->d_tile_count, b->d_tile_offset,
-                       b->d_chunk_offset, (long long)nt, b->chunk_cap, b->d_flags);
-    BL_HIP(hipGetLastError());
+    BL_TRY(launch_tile_scan(b->d_tile_count, b->d_tile_offset, b->d_chunk_offset, nt, b->chunk_cap, b->d_flags,
+                            b->d_scan, s));
     if (N > 0) {
         hipLaunchKernelGGL(k_bbin_scatter, dim3(nb), dim3(kBinThreads), 0, s, x, (long long)N, b->d_node_tile,
-                           b->d_tile_offset, b->d_tile_cursor, b->d_perm, b->d_xs);
+                           b->d_tile_offset, b->d_tile_cursor, b->d_perm, b->d_xs, int(nt));
         BL_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_bchunk_fill, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, s, b->d_tile_count,

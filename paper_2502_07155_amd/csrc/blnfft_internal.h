@@ -144,6 +144,7 @@ struct Plan {
     double edge_k = 1.0;           // edge exponent of the weight polynomials (edge_exponent)
     bool fft_ok = true;            // steps 1-2 and the adjoint available for this L
     int fft_lines[2][3] = {{0, 0, 0}, {0, 0, 0}};   // [forward, adjoint][axis]: tuned lines per workgroup
+    int fft_radix[2][3] = {{0, 0, 0}, {0, 0, 0}};   // the same for the values per thread (4 or 16)
     int tune_fft_source = 0;       // 0 heuristic (or override), 1 measured, 2 from the tuning cache
     int tune_tile_source = 0;      // the same for the short-sum tiles and chunk capacity
     int64_t tuned_N = -1;          // node count the tiles were tuned (or looked up) for
@@ -178,6 +179,7 @@ struct Plan {
     int32_t* d_tile_offset = nullptr;
     int32_t* d_tile_cursor = nullptr;
     int32_t* d_chunk_offset = nullptr;
+    void* d_scan = nullptr;        // block sums of the tile scans (tile_scan_scratch_bytes)
     int4* d_chunks = nullptr;      // {tile, start, count, 0}
     int64_t chunk_alloc = 0;
     int64_t nchunks = 0;
@@ -259,6 +261,11 @@ bl_status launch_gather(Plan& p, const void* theta, void* f);
 bl_status launch_weights(Plan& p);
 // Binning of nodes.
 bl_status launch_binning(Plan& p, const void* x, int64_t N);
+// Device-wide exclusive scans of per-tile node counts and chunk counts ceil(count / cap);
+// flags[2] receives the total chunk count.  scratch: tile_scan_scratch_bytes(ntiles).
+bl_status launch_tile_scan(const int32_t* count, int32_t* offset, int32_t* chunk_off, int64_t ntiles, int cap,
+                           unsigned long long* flags, void* scratch, hipStream_t stream);
+size_t tile_scan_scratch_bytes(int64_t ntiles);
 // Adjoint spreading Psi^T g (or B^T g) onto `grid` (L^d, centred), which it overwrites:
 // per-chunk boxes into `boxes` (spread_boxes_bytes), then their fixed-order merge.
 bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes);
@@ -271,8 +278,8 @@ size_t noalloc_scratch_bytes();
 // centred order; dir +1 forward (band -> grid), -1 adjoint (grid -> band).
 bl_status launch_czt_pass(Plan& p, int dir, const void* in, void* out, int outer, int inner, int Min,
                           int Mout, PassTypes t, int lines);
-// Autotuner (fft.hip): time every forward and adjoint pass of the plan for 1, 2, ..., 16
-// lines per workgroup on the given scratch buffers (each >= L^d complex of the pass type)
+// Autotuner (fft.hip): time every forward and adjoint pass of the plan for 1, 2, ..., 64
+// lines per workgroup and 4 or 16 values per thread on the given scratch buffers (each >= L^d complex of the pass type)
 // and keep the fastest in p.fft_lines.
 bl_status tune_fft_lines(Plan& p, void* buf_in, void* buf_out);
 // autotune.cpp: FFT lines per workgroup at plan creation (cached), and the cache of the

@@ -46,6 +46,7 @@ struct PassArgs {
     int rlast;              // trailing radix (2, 4 or 8 for E = 16; 2 for E = 4), 1 for none
     int tw_off[kMaxStages];
     int lines;              // lines per workgroup chosen by the autotuner (0: heuristic)
+    int radix;              // values per thread (4 or 16) chosen by the autotuner (0: heuristic)
 };
 
 // Butterfly g of a stage -> (line b, butterfly index j within the line).  Contiguous
@@ -389,7 +390,12 @@ bl_status run_pass_e(Plan& p, PassArgs a) {
 template <typename TI, typename R, typename TO, typename TW, int DIR>
 bl_status run_pass(Plan& p, PassArgs a) {
     const int64_t lines = int64_t(a.outer) * a.inner;
-    const int E = choose_radix(p, lines);
+    int E = choose_radix(p, lines);
+    if (a.radix == 4 || a.radix == 16) E = a.radix;
+    if (E == 4 && p.L / 4 > 512) {
+        set_error("radix-4 passes take lines of at most 2048 points");
+        return BL_EUNSUPPORTED;
+    }
     const FftStages& st = E == 16 ? p.st16 : p.st4;
     a.nmain = st.nmain;
     a.rlast = st.rlast;
@@ -450,6 +456,7 @@ bl_status forward_fft(Plan& p, const void* fhat) {
         a.Min = int(p.M);
         a.Mout = int(p.L);
         a.lines = p.fft_lines[0][axis];
+        a.radix = p.fft_radix[0][axis];
         BL_TRY(dispatch_pass<+1>(p, a, t));
         src = dst;
     }
@@ -475,6 +482,7 @@ bl_status adjoint_fft(Plan& p, const void* grid, void* fhat_out) {
         a.Min = int(p.L);
         a.Mout = int(p.M);
         a.lines = p.fft_lines[1][axis];
+        a.radix = p.fft_radix[1][axis];
         BL_TRY(dispatch_pass<-1>(p, a, t));
         src = dst;
     }
@@ -484,8 +492,9 @@ bl_status adjoint_fft(Plan& p, const void* grid, void* fhat_out) {
 // Average time (ms) of `reps` launches of one pass with `lines` lines per workgroup; a
 // negative value when that line count is not valid for the pass.
 template <int DIR>
-double time_pass(Plan& p, PassArgs a, PassTypes t, int lines, int reps, hipEvent_t e0, hipEvent_t e1) {
+double time_pass(Plan& p, PassArgs a, PassTypes t, int lines, int radix, int reps, hipEvent_t e0, hipEvent_t e1) {
     a.lines = lines;
+    a.radix = radix;
     if (dispatch_pass<DIR>(p, a, t) != BL_OK) return -1.0;   // warm-up (and validity)
     if (hipEventRecord(e0, p.stream) != hipSuccess) return -1.0;
     for (int r = 0; r < reps; ++r)
@@ -520,18 +529,24 @@ bl_status tune_fft_lines(Plan& p, void* buf_in, void* buf_out) {
             for (int k = axis + 1; k < d; ++k) a.inner *= int(dir == 0 ? p.L : p.M);
             a.Min = int(dir == 0 ? p.M : p.L);
             a.Mout = int(dir == 0 ? p.L : p.M);
-            int best = 0;
+            int best = 0, best_radix = 0;
             double best_ms = 0.0;
-            for (int lines = 1; lines <= 16; lines *= 2) {
-                const double ms = dir == 0 ? time_pass<+1>(p, a, t, lines, 5, e0, e1)
-                                           : time_pass<-1>(p, a, t, lines, 5, e0, e1);
-                if (ms > 0.0 && (best == 0 || ms < best_ms)) {
-                    best = lines;
-                    best_ms = ms;
+            // the chirp-z passes have one radix (16); the Stockham passes try 4 and 16
+            for (int radix : {4, 16}) {
+                if (p.czt.on && radix == 4) continue;
+                for (int lines = 1; lines <= 64; lines *= 2) {
+                    const double ms = dir == 0 ? time_pass<+1>(p, a, t, lines, radix, 5, e0, e1)
+                                               : time_pass<-1>(p, a, t, lines, radix, 5, e0, e1);
+                    if (ms > 0.0 && (best == 0 || ms < best_ms)) {
+                        best = lines;
+                        best_radix = p.czt.on ? 0 : radix;
+                        best_ms = ms;
+                    }
                 }
             }
             (void)hipGetLastError();
             p.fft_lines[dir][axis] = best;
+            p.fft_radix[dir][axis] = best_radix;
         }
     }
     hipEventDestroy(e0);

@@ -12,6 +12,7 @@
 // J_{L,m}(x) have sinc(+-m pi) phi(+-m/L) = 0.  The offset u = L x - l = theta + m - 1 - o,
 // and sin(pi u) = (-1)^{m-1-o} sin(pi theta), so one sin per node and dimension serves all
 // 2m weights; sin(pi theta) is reduced to [0, 1/2] by reflection.
+#include <algorithm>
 #include <cstdlib>
 
 #include "blnfft_internal.h"
@@ -144,40 +145,125 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_count(BinArgs a, int ntiles
     }
 }
 
-// One workgroup: exclusive scans of node counts and of chunk counts per tile.
-__global__ void __launch_bounds__(1024) k_tile_scan(const int32_t* count, int32_t* offset,
-                                                    int32_t* chunk_off, int64_t ntiles, int cap,
-                                                    unsigned long long* flags) {
-    __shared__ long long s1[1024];
-    __shared__ long long s2[1024];
-    const int tid = threadIdx.x, NT = blockDim.x;
-    int64_t per = (ntiles + NT - 1) / NT;
-    int64_t beg = tid * per, end = beg + per < ntiles ? beg + per : ntiles;
-    long long a = 0, b = 0;
-    for (int64_t i = beg; i < end; ++i) {
-        a += count[i];
-        b += (count[i] + cap - 1) / cap;
-    }
-    s1[tid] = a;
-    s2[tid] = b;
+}  // namespace
+
+// ---------------------------------------------------------------- tile scans
+// Exclusive scans of the node counts and of the chunk counts ceil(count / cap) per tile,
+// device-wide in three kernels: per-block sums over kScanBlock tiles, one workgroup
+// scanning the block sums (and storing the total chunk count in flags[2]), and the
+// per-block scans offset by their block's prefix.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanBlock = kScanThreads * kScanPer;
+
+namespace {
+
+// Inclusive scan of v over the workgroup (Hillis-Steele in LDS); returns the total in tot.
+template <int NT>
+__device__ __forceinline__ long long block_scan(long long v, long long* sh, long long& tot) {
+    sh[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < NT; off *= 2) {
-        long long va = tid >= off ? s1[tid - off] : 0;
-        long long vb = tid >= off ? s2[tid - off] : 0;
+        const long long u = int(threadIdx.x) >= off ? sh[threadIdx.x - off] : 0;
         __syncthreads();
-        s1[tid] += va;
-        s2[tid] += vb;
+        sh[threadIdx.x] += u;
         __syncthreads();
     }
-    long long ea = s1[tid] - a, eb = s2[tid] - b;
-    for (int64_t i = beg; i < end; ++i) {
-        offset[i] = int32_t(ea);
-        chunk_off[i] = int32_t(eb);
-        ea += count[i];
-        eb += (count[i] + cap - 1) / cap;
-    }
-    if (tid == NT - 1) flags[2] = (unsigned long long)s2[NT - 1];
+    const long long r = sh[threadIdx.x];
+    tot = sh[NT - 1];
+    __syncthreads();
+    return r;
 }
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_partial(const int32_t* count, int64_t ntiles, int cap,
+                                                               long long* bsum) {
+    __shared__ long long sa[kScanThreads], sb[kScanThreads];
+    const int64_t t0 = int64_t(blockIdx.x) * kScanBlock + int64_t(threadIdx.x) * kScanPer;
+    long long a = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (t0 + k < ntiles) {
+            const int c = count[t0 + k];
+            a += c;
+            b += (c + cap - 1) / cap;
+        }
+    }
+    long long ta, tb;
+    block_scan<kScanThreads>(a, sa, ta);
+    block_scan<kScanThreads>(b, sb, tb);
+    if (threadIdx.x == 0) {
+        bsum[2 * blockIdx.x] = ta;
+        bsum[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_blocks(long long* bsum, int64_t nb, unsigned long long* flags) {
+    __shared__ long long sa[1024], sb[1024];
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t beg = int64_t(threadIdx.x) * per, end = min(beg + per, nb);
+    long long a = 0, b = 0;
+    for (int64_t i = beg; i < end; ++i) {
+        a += bsum[2 * i];
+        b += bsum[2 * i + 1];
+    }
+    long long ta, tb;
+    long long ea = block_scan<1024>(a, sa, ta) - a, eb = block_scan<1024>(b, sb, tb) - b;
+    for (int64_t i = beg; i < end; ++i) {
+        const long long va = bsum[2 * i], vb = bsum[2 * i + 1];
+        bsum[2 * i] = ea;
+        bsum[2 * i + 1] = eb;
+        ea += va;
+        eb += vb;
+    }
+    if (threadIdx.x == 0) flags[2] = (unsigned long long)tb;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_final(const int32_t* count, int64_t ntiles, int cap,
+                                                             const long long* bsum, int32_t* offset,
+                                                             int32_t* chunk_off) {
+    __shared__ long long sa[kScanThreads], sb[kScanThreads];
+    const int64_t t0 = int64_t(blockIdx.x) * kScanBlock + int64_t(threadIdx.x) * kScanPer;
+    int c[kScanPer];
+    long long a = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        c[k] = t0 + k < ntiles ? count[t0 + k] : 0;
+        a += c[k];
+        b += (c[k] + cap - 1) / cap;
+    }
+    long long ta, tb;
+    long long ea = block_scan<kScanThreads>(a, sa, ta) - a + bsum[2 * blockIdx.x];
+    long long eb = block_scan<kScanThreads>(b, sb, tb) - b + bsum[2 * blockIdx.x + 1];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (t0 + k < ntiles) {
+            offset[t0 + k] = int32_t(ea);
+            chunk_off[t0 + k] = int32_t(eb);
+        }
+        ea += c[k];
+        eb += (c[k] + cap - 1) / cap;
+    }
+}
+
+}  // namespace
+
+size_t tile_scan_scratch_bytes(int64_t ntiles) {
+    return size_t(2 * ((ntiles + kScanBlock - 1) / kScanBlock + 1)) * sizeof(long long);
+}
+
+bl_status launch_tile_scan(const int32_t* count, int32_t* offset, int32_t* chunk_off, int64_t ntiles, int cap,
+                           unsigned long long* flags, void* scratch, hipStream_t stream) {
+    const int64_t nb = std::max<int64_t>(1, (ntiles + kScanBlock - 1) / kScanBlock);
+    long long* bsum = static_cast<long long*>(scratch);
+    hipLaunchKernelGGL(k_scan_partial, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, count, ntiles, cap, bsum);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, stream, bsum, nb, flags);
+    hipLaunchKernelGGL(k_scan_final, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, count, ntiles, cap,
+                       static_cast<const long long*>(bsum), offset, chunk_off);
+    BL_HIP(hipGetLastError());
+    return BL_OK;
+}
+
+namespace {
 
 template <typename R, int D>
 __global__ void __launch_bounds__(kBinThreads) k_bin_scatter(const R* __restrict__ x, int64_t N,
@@ -748,9 +834,8 @@ bl_status launch_binning(Plan& p, const void* x, int64_t N) {
         }
         BL_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, p.stream, p.d_tile_count,
-                       p.d_tile_offset, p.d_chunk_offset, p.ntiles, p.chunk_cap, p.d_flags);
-    BL_HIP(hipGetLastError());
+    BL_TRY(launch_tile_scan(p.d_tile_count, p.d_tile_offset, p.d_chunk_offset, p.ntiles, p.chunk_cap, p.d_flags,
+                            p.d_scan, p.stream));
     if (N > 0) {
         if (dbl) {
             const double* xd = static_cast<const double*>(x);

@@ -182,6 +182,7 @@ class Plan:
                 "workspace_bytes": s.workspace_bytes, "beta": s.beta,
                 "weight_fit_err": s.weight_fit_err,
                 "fft_lines": (tuple(s.fft_lines[0:3]), tuple(s.fft_lines[3:6])),
+                "fft_radix": (tuple(s.fft_radix[0:3]), tuple(s.fft_radix[3:6])),
                 "tuned": {"fft": int(s.tuned[0]), "tiles": int(s.tuned[1])}}
 
     def close(self) -> None:
