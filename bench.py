@@ -122,6 +122,28 @@ def time_calls(torch, fn, steps: int, warmup: int, stream) -> float:
     return start.elapsed_time(end) / steps
 
 
+def pass_bytes(d, M, L, csize):
+    """(read, written) bytes of each pruned forward pass, in pass order (last axis first)."""
+    out = []
+    for axis in range(d - 1, -1, -1):
+        out.append((M ** (axis + 1) * L ** (d - 1 - axis) * csize, M ** axis * L ** (d - axis) * csize))
+    return out
+
+
+def copy_floor_ms(torch, passes) -> float:
+    """Time of plain device copies that move the same bytes as the FFT passes (one copy of
+    (read + written) / 2 bytes per pass, each launched on its own): the latency and bandwidth
+    floor a pass kernel of that traffic is compared with."""
+    total = 0.0
+    for rd, wr in passes:
+        n = (rd + wr) // 2
+        a = torch.empty(n // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        total += time_calls(torch, lambda: b.copy_(a), 50, 5, torch.cuda.current_stream())
+        del a, b
+    return total
+
+
 def copy_bandwidth(torch, nbytes: int = 1 << 28, reps: int = 20) -> float:
     """Measured HBM bandwidth of a plain device copy (bytes read + written per second, GB/s),
     the achievable figure beside the nominal peak."""
@@ -266,7 +288,39 @@ def plan_shape(plan) -> dict:
             "tuned": st["tuned"]}
 
 
-def leg_plan(name, prec, steps, warmup, checks: list, sample=5000):
+def reference_check(rec: dict, p, f, kind: str):
+    """The workload's own reference, applied to the GPU output by the oracle leg: the direct
+    trigonometric sum on the truncated-domain nodes (boundary nodes reported apart), or, for
+    fhat = 1 on the band, the Dirichlet product prod_t D_M(x_t) on 20000 sampled nodes
+    (relative to max |D| = M^d).  Bound: d e^{-beta}, beta = pi m (L - M) / L."""
+    import numpy as np
+
+    import workloads as W
+    if kind == "direct_sum":
+        got, x = f.copy(), p.x.copy()
+    else:
+        idx = np.sort(W.rng_for(23).choice(p.N, size=min(20000, p.N), replace=False))
+        got, x = f[idx].copy(), p.x[idx].copy()
+    fhat, d, M, L, m = p.fhat, p.d, p.M, p.L, p.m
+
+    def check(O):
+        inside = O.in_truncated_domain(x, L, m)
+        rec["reference_bound_d_exp_minus_beta"] = d * float(np.exp(-O.default_beta(M, L, m)))
+        if kind == "direct_sum":
+            ref = O.direct_sum(fhat, x)
+            rec["rel_err_inf_vs_direct_sum_truncated_domain"] = O.rel_err_inf(got[inside], ref[inside])
+            if (~inside).any():
+                rec["rel_err_inf_vs_direct_sum_boundary_nodes"] = float(
+                    np.max(np.abs(got[~inside] - ref[~inside])) / np.max(np.abs(ref[inside])))
+            rec["truncated_domain_nodes"] = int(inside.sum())
+        else:
+            D = O.dirichlet(x[inside], M)
+            rec["err_vs_dirichlet_product_rel_M_pow_d"] = float(np.max(np.abs(got[inside] - D)) / float(M) ** d)
+            rec["dirichlet_sampled_nodes"] = int(inside.sum())
+    return check
+
+
+def leg_plan(name, prec, steps, warmup, checks: list, sample=5000, reference: str | None = None):
     p, plan, f, ms, gms, plan_ms = run_plan(name, prec, steps, warmup)
     shape = plan_shape(plan)
     plan.close()
@@ -276,6 +330,8 @@ def leg_plan(name, prec, steps, warmup, checks: list, sample=5000):
            "fft_frac_of_hbm_peak": ab["fft"] / (plan.fft_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "plan_ms": plan_ms, "precision": prec, "shape": shape}
     checks.append(accuracy_check(rec, p, f, sample))
+    if reference:
+        checks.append(reference_check(rec, p, f, reference))
     return rec
 
 
@@ -526,6 +582,15 @@ def leg_batched(steps, warmup, checks: list):
     out = torch.empty(bp.total_N, dtype=torch.complex64, device="cuda")
     ms = time_calls(torch, lambda: bp.forward(fhat, out), steps, warmup, bp.stream)
     f = out.cpu().numpy().astype(np.complex128)
+    # a second batch of the same shapes reads its tile edge from the tuning cache
+    bp2 = BatchPlan([i.M for i in insts], [i.L for i in insts], [i.m for i in insts],
+                    [i.x.size for i in insts], precision="f32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bp2.set_nodes(x)
+    torch.cuda.synchronize()
+    plan_ms_cached = (time.perf_counter() - t0) * 1e3
+    bp2.close()
     rng = W.rng_for(19)
     picks = []
     for i in rng.choice(len(insts), 32, replace=False):
@@ -534,6 +599,7 @@ def leg_batched(steps, warmup, checks: list):
         picks.append((inst, idx, f[bp.node_offsets[i]:bp.node_offsets[i + 1]][idx].copy()))
     bp.close()
     rec = {"value": bp.total_N / (ms * 1e-3), "ms_per_step": ms, "plan_ms": plan_ms,
+           "plan_ms_cached_tuning": plan_ms_cached,
            "instances": len(insts), "total_nodes": bp.total_N, "precision": "f32"}
 
     def check(O):
@@ -848,9 +914,12 @@ def main():
                          "traffic": measured_fft_traffic(args.workload, prec),
                          "algorithmic_bytes_per_launch": ab["fft"],
                          "ms_per_launch": fft_ms,
+                         "copy_floor_ms": None if args.headline_only else copy_floor_ms(
+                             torch, pass_bytes(p.d, p.M, p.L, csize)),
                          "note": "all passes of one transform between HIP events on the plan's stream "
                                  "(bl_samples); algorithmic bytes: every pruned pass reads and writes "
-                                 "its lines once in the data type"},
+                                 "its lines once in the data type; copy_floor_ms: plain device copies "
+                                 "moving the same bytes, one per pass"},
         "hbm": {"algorithmic_bytes": ab, "deconv_fft_GBs": ab["fft"] / (fft_ms * 1e-3) / 1e9,
                 "gather_GBs": ab["gather"] / (gms * 1e-3) / 1e9, "peak_GBs": HBM_PEAK_GBS,
                 "copy_GBs": None if args.headline_only else copy_bandwidth(torch),
@@ -873,10 +942,16 @@ def main():
         legs = {}
         short = max(5, args.steps // 5)
         legs["d2_M512_L1024_m5_N1M_f64"] = leg_plan(HEADLINE, "f64", short, 2, checks)
+        legs["d2_M512_L1024_m5_N1M_f32d"] = leg_plan(HEADLINE, "f32d", short, 2, checks)
+        legs["d2_M512_L1024_m5_N1M_f32"] = leg_plan(HEADLINE, "f32", short, 2, checks)
         legs["d2_M512_L1024_m5_N1M_nfft"] = leg_nfft(short, 2, f, p, checks)
-        legs["d1_M256_L512_m6_N1k_f64"] = leg_plan("d1_M256_L512_m6_N1k", "f64", short, 2, checks, 1000)
-        legs["d3_M128_L256_m4_N2M_f32c"] = leg_plan("d3_M128_L256_m4_N2M", "f32c", short, 2, checks, 3000)
-        legs["d3_M128_L256_m4_N2M_f64"] = leg_plan("d3_M128_L256_m4_N2M", "f64", short, 2, checks, 3000)
+        legs["d1_M256_L512_m6_N1k_f64"] = leg_plan("d1_M256_L512_m6_N1k", "f64", short, 2, checks, 1000,
+                                                   reference="direct_sum")
+        legs["d3_M128_L256_m4_N2M_f32c"] = leg_plan("d3_M128_L256_m4_N2M", "f32c", short, 2, checks, 3000,
+                                                    reference="dirichlet")
+        legs["d3_M128_L256_m4_N2M_f32d"] = leg_plan("d3_M128_L256_m4_N2M", "f32d", short, 2, checks, 3000)
+        legs["d3_M128_L256_m4_N2M_f64"] = leg_plan("d3_M128_L256_m4_N2M", "f64", short, 2, checks, 3000,
+                                                   reference="dirichlet")
         legs["batched_512_d1_f32"] = leg_batched(short, 2, checks)
         legs["d2_M256_L512_m6_N200k_fwd_bwd_f32"] = leg_differentiation(short, 2)
         legs["d2_M512_L1024_m5_N1M_adjoint_f32c"] = leg_adjoint(HEADLINE, "f32c", short, 2, checks)

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -111,6 +112,10 @@ void free_plan(Plan& p) {
     hipFree(p.d_chunk_offset);
     hipFree(p.d_scan);
     p.d_scan = nullptr;
+    hipFree(p.d_cov);
+    p.d_cov = nullptr;
+    hipFree(p.d_reach);
+    p.d_reach = nullptr;
     hipFree(p.d_flags);
     hipFree(p.d_wpre);
     p.d_wpre = nullptr;
@@ -170,6 +175,62 @@ int64_t tiles_for(const Plan& p, int T) {
     return n;
 }
 
+// Coverage table of the adjoint's box merge for tile edge T: per coordinate p of a
+// dimension, its tile and every (tile, position) whose box (tile + halo, tile t spanning
+// grid points t T - m + 1 ... t T + T + m - 2) covers p, periodically for Algorithm 2.1.
+// Empty when some coordinate has more than kCovMax covering boxes.
+std::vector<int> coverage_table(const Plan& p, int T) {
+    const int L = int(p.L), m = p.m, W = T + 2 * p.m - 1, tpd = (L + T - 1) / T;
+    std::vector<int> tab(size_t(L) * kCovRow, 0);
+    const int s_lo = p.method == BL_NFFT ? -1 : 0, s_hi = p.method == BL_NFFT ? 2 : 0;
+    for (int q = 0; q < L; ++q) {
+        int* row = &tab[size_t(q) * kCovRow];
+        row[0] = q / T;
+        int n = 0;
+        for (int s = s_lo; s <= s_hi; ++s) {
+            const int u = q + s * L;   // unwrapped coordinate: box position c = u - (t T - m + 1)
+            // c in [0, W) <=> t T in [u + m - W, u + m - 1]
+            const int tlo = std::max(0, (u + m - W + T - 1 + 2 * L * T) / T - 2 * L);   // ceil, any sign
+            const int thi = std::min(tpd - 1, u + m - 1 < 0 ? -1 : (u + m - 1) / T);
+            for (int t = tlo; t <= thi; ++t) {
+                const int c = u - (t * T - m + 1);
+                if (c < 0 || c >= W) continue;
+                if (n == kCovMax) return std::vector<int>();
+                // offset of the covering tile from the coordinate's own tile, wrapped for the
+                // periodic sums into [-kNbR, kNbR] (the merge stages that neighbourhood)
+                int dt = t - q / T;
+                if (p.method == BL_NFFT) {
+                    if (dt > kNbR) dt -= tpd;
+                    if (dt < -kNbR) dt += tpd;
+                    if (((q / T + dt) % tpd + tpd) % tpd != t) return std::vector<int>();
+                }
+                if (dt < -kNbR || dt > kNbR) return std::vector<int>();
+                row[2 + 2 * n] = dt;
+                row[3 + 2 * n] = c;
+                ++n;
+            }
+        }
+        row[1] = n;
+    }
+    // the merge's reach flags mark, per box, the distinct tiles of its W coordinates: at most
+    // eight per dimension (kReachList in spread.hip), else the general merge is used
+    for (int t = 0; t < tpd; ++t) {
+        int distinct = 0, last = -1;
+        std::vector<int> seen;
+        for (int c = t * T - m + 1; c <= t * T + T + m - 2; ++c) {
+            int q = c;
+            if (p.method == BL_NFFT) q = ((q % L) + L) % L;
+            else if (q < 0 || q >= L) continue;
+            const int tt = q / T;
+            if (tt == last || std::find(seen.begin(), seen.end(), tt) != seen.end()) continue;
+            last = tt;
+            seen.push_back(tt);
+            if (++distinct > 8) return std::vector<int>();
+        }
+    }
+    return tab;
+}
+
 // Sets the tile edge and the chunk capacity, growing the per-tile arrays when needed.
 bl_status apply_tiles(Plan& p, int T, int cap) {
     p.ntiles = 1;
@@ -179,6 +240,16 @@ bl_status apply_tiles(Plan& p, int T, int cap) {
         p.ntiles *= p.tiles_per_dim[t];
     }
     p.chunk_cap = cap;
+    // the adjoint merge's coverage table for this tile edge (empty: the general merge)
+    BL_HIP(hipStreamSynchronize(p.stream));
+    hipFree(p.d_cov);
+    p.d_cov = nullptr;
+    const std::vector<int> cov = coverage_table(p, T);
+    if (!cov.empty()) {
+        size_t extra = 0;
+        BL_TRY(dev_alloc(&p.d_cov, sizeof(int) * cov.size(), &extra));
+        BL_HIP(hipMemcpy(p.d_cov, cov.data(), sizeof(int) * cov.size(), hipMemcpyHostToDevice));
+    }
     if (p.ntiles <= p.tile_alloc) return BL_OK;
     BL_HIP(hipStreamSynchronize(p.stream));
     for (int32_t** a : {&p.d_tile_count, &p.d_tile_offset, &p.d_tile_cursor, &p.d_chunk_offset}) {
@@ -187,12 +258,15 @@ bl_status apply_tiles(Plan& p, int T, int cap) {
     }
     hipFree(p.d_scan);
     p.d_scan = nullptr;
+    hipFree(p.d_reach);
+    p.d_reach = nullptr;
     p.workspace_bytes -= size_t(p.tile_alloc) * 4 * sizeof(int32_t) + (p.tile_alloc ? tile_scan_scratch_bytes(p.tile_alloc) : 0);
     p.tile_alloc = 0;
     size_t extra = 0;
     for (int32_t** a : {&p.d_tile_count, &p.d_tile_offset, &p.d_tile_cursor, &p.d_chunk_offset})
         BL_TRY(dev_alloc(a, sizeof(int32_t) * size_t(p.ntiles), &extra));
     BL_TRY(dev_alloc(reinterpret_cast<char**>(&p.d_scan), tile_scan_scratch_bytes(p.ntiles), &extra));
+    BL_TRY(dev_alloc(&p.d_reach, size_t(p.ntiles), &extra));
     p.tile_alloc = p.ntiles;
     p.workspace_bytes += extra;
     return BL_OK;
@@ -220,6 +294,7 @@ double time_gather(Plan& p, void* f, hipEvent_t e0, hipEvent_t e1) {
 bl_status bin_tuned(Plan& p, const void* x, int64_t N) {
     if (!tile_tuning_wanted(p, N) || (p.tuned_N == N && p.tune_tile_source != 0))
         return launch_binning(p, x, N);
+    p.N = N;   // the short-sum kernel timed below runs over p.N nodes
     BL_TRY(apply_tiles(p, default_tile(p), 1024));
     BL_TRY(launch_binning(p, x, N));
     std::vector<int32_t> cnt(size_t(p.ntiles));
@@ -250,6 +325,9 @@ bl_status bin_tuned(Plan& p, const void* x, int64_t N) {
             if (st == BL_OK) st = launch_binning(p, x, N);
             if (st != BL_OK) break;
             const double ms = time_gather(p, f, e0, e1);
+            if (std::getenv("BL_TUNE_VERBOSE"))
+                std::fprintf(stderr, "blnfft tune tiles: d=%d L=%lld m=%d tile=%d cap=%d chunks=%lld: %.2f us\n", p.d,
+                             (long long)p.L, p.m, cands[i].first, cands[i].second, (long long)p.nchunks, ms * 1e3);
             if (ms > 0.0 && (best_ms < 0.0 || ms < best_ms)) {
                 best_ms = ms;
                 T = cands[i].first;
@@ -597,7 +675,11 @@ bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev) {
         p.N_cap = ncap;
         p.chunk_alloc = cb;
     }
-    BL_TRY(bin_tuned(p, x_dev, N));
+    const bl_status st = bin_tuned(p, x_dev, N);
+    if (st != BL_OK) {
+        p.N = 0;
+        return st;
+    }
     p.N = N;
     p.have_nodes = true;
     return BL_OK;

@@ -38,10 +38,6 @@ std::map<std::string, std::vector<int>> g_cache;   // entries of the file g_path
 bool g_loaded = false;
 std::string g_path;
 
-bool tuning_enabled() {
-    const char* e = std::getenv("BL_AUTOTUNE");
-    return !(e && e[0] == '0');
-}
 
 std::string cache_path() {
     if (const char* e = std::getenv("BL_TUNE_CACHE")) return std::string(e) == "off" ? std::string() : std::string(e);
@@ -109,7 +105,14 @@ void save_cache_locked() {
     std::rename(tmp.c_str(), path.c_str());
 }
 
-bool lookup(const std::string& key, std::vector<int>* vals) {
+}  // namespace
+
+bool tuning_enabled() {
+    const char* e = std::getenv("BL_AUTOTUNE");
+    return !(e && e[0] == '0');
+}
+
+bool tune_lookup(const std::string& key, std::vector<int>* vals) {
     std::lock_guard<std::mutex> lock(g_mu);
     load_cache_locked();
     auto it = g_cache.find(key);
@@ -118,14 +121,14 @@ bool lookup(const std::string& key, std::vector<int>* vals) {
     return true;
 }
 
-void store(const std::string& key, const std::vector<int>& vals) {
+void tune_store(const std::string& key, const std::vector<int>& vals) {
     std::lock_guard<std::mutex> lock(g_mu);
     load_cache_locked();
     g_cache[key] = vals;
     save_cache_locked();
 }
 
-std::string device_tag(int device) {
+std::string tune_device_tag(int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
     std::string arch = prop.gcnArchName;
@@ -133,6 +136,8 @@ std::string device_tag(int device) {
     if (colon != std::string::npos) arch = arch.substr(0, colon);
     return arch + "x" + std::to_string(prop.multiProcessorCount);
 }
+
+namespace {
 
 const char* prec_name(bl_precision p) {
     switch (p) {
@@ -145,7 +150,7 @@ const char* prec_name(bl_precision p) {
 
 std::string plan_key(const Plan& p, const char* what) {
     std::ostringstream k;
-    k << what << "|" << device_tag(p.device) << "|d" << p.d << "|M" << p.M << "|L" << p.L << "|m" << p.m << "|"
+    k << what << "|" << tune_device_tag(p.device) << "|d" << p.d << "|M" << p.M << "|L" << p.L << "|m" << p.m << "|"
       << prec_name(p.prec) << "|" << (p.method == BL_NFFT ? "nfft" : "shannon") << "|"
       << (p.czt.on ? "czt" : "pow2");
     return k.str();
@@ -157,7 +162,7 @@ bl_status autotune_fft(Plan& p) {
     if (!p.fft_ok || !tuning_enabled() || std::getenv("BL_FFT_LINES") || std::getenv("BL_CZT_LINES")) return BL_OK;
     const std::string key = plan_key(p, "fft");
     std::vector<int> v;
-    if (lookup(key, &v) && v.size() == 12) {
+    if (tune_lookup(key, &v) && v.size() == 12) {
         for (int i = 0; i < 6; ++i) {
             p.fft_lines[i / 3][i % 3] = v[i];
             p.fft_radix[i / 3][i % 3] = v[6 + i];
@@ -189,7 +194,7 @@ bl_status autotune_fft(Plan& p) {
         v[i] = p.fft_lines[i / 3][i % 3];
         v[6 + i] = p.fft_radix[i / 3][i % 3];
     }
-    store(key, v);
+    tune_store(key, v);
     p.tune_fft_source = 1;
     return BL_OK;
 }
@@ -204,14 +209,14 @@ bool tile_tuning_wanted(const Plan& p, int64_t N) {
 
 bool tile_cache_lookup(const Plan& p, int density, int cluster, int* T, int* cap) {
     std::vector<int> v;
-    if (!lookup(tile_key(p, density, cluster), &v) || v.size() != 2) return false;
+    if (!tune_lookup(tile_key(p, density, cluster), &v) || v.size() != 2) return false;
     *T = v[0];
     *cap = v[1];
     return true;
 }
 
 void tile_cache_store(const Plan& p, int density, int cluster, int T, int cap) {
-    store(tile_key(p, density, cluster), std::vector<int>{T, cap});
+    tune_store(tile_key(p, density, cluster), std::vector<int>{T, cap});
 }
 
 }  // namespace bl

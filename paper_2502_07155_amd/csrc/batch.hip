@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -369,22 +370,6 @@ constexpr int kBinThreads = 256;
 constexpr int kBinPer = 16;
 constexpr int kLdsBins = 8192;
 
-__device__ __forceinline__ int node_tile_of(const BBinArgs& a, long long j, unsigned& invalid, unsigned& outside) {
-    const int i = find_instance(a.node_off, a.count, j);
-    const InstDesc d = a.desc[i];
-    float xv = a.x[j];
-    if (!(xv >= -0.5f && xv < 0.5f)) {
-        ++invalid;
-        xv = 0.0f;
-    }
-    const float lim = 0.5f - float(d.m) / float(d.L);
-    if (!(xv >= -lim && xv < lim)) ++outside;
-    int n;
-    float th;
-    dev::cell_of<float>(xv, d.L, n, th);
-    return d.tile_base + (n + d.L / 2) / a.tile;
-}
-
 // Smallest and largest tile among the workgroup's nodes (tl < 0: none), uniform over the
 // workgroup; hi < lo when it has no nodes.
 __device__ __forceinline__ void tile_range(const int* tl, int& lo, int& hi) {
@@ -420,12 +405,32 @@ __global__ void __launch_bounds__(kBinThreads) k_bbin_count(BBinArgs a, int ntil
     const long long j0 = (long long)blockIdx.x * (kBinThreads * kBinPer) + threadIdx.x;
     int tl[kBinPer];
     unsigned invalid = 0, outside = 0;
+    // A thread's nodes increase by kBinThreads, so its instance is found once by bisection
+    // and then advanced; the instance's parameters are reloaded only when it changes.
+    int inst = j0 < a.N ? find_instance(a.node_off, a.count, j0) : 0;
+    long long next = a.node_off[inst + 1];
+    InstDesc d = a.desc[inst];
 #pragma unroll
     for (int k = 0; k < kBinPer; ++k) {
         const long long j = j0 + (long long)k * kBinThreads;
         tl[k] = -1;
         if (j < a.N) {
-            tl[k] = node_tile_of(a, j, invalid, outside);
+            if (j >= next) {
+                while (j >= a.node_off[inst + 1]) ++inst;
+                next = a.node_off[inst + 1];
+                d = a.desc[inst];
+            }
+            float xv = a.x[j];
+            if (!(xv >= -0.5f && xv < 0.5f)) {
+                ++invalid;
+                xv = 0.0f;
+            }
+            const float lim = 0.5f - float(d.m) / float(d.L);
+            if (!(xv >= -lim && xv < lim)) ++outside;
+            int n;
+            float th;
+            dev::cell_of<float>(xv, d.L, n, th);
+            tl[k] = d.tile_base + (n + d.L / 2) / a.tile;
             a.node_tile[j] = tl[k];
         }
     }
@@ -879,7 +884,36 @@ bl_status batch_bin(bl_batch_s* b, const float* x, int tile) {
 
 // Time the short sums (on the zeroed samples theta) for each candidate tile edge and keep
 // the fastest.  Runs once per batch, at its first node binding.
+// Key of the batch in the tuning cache: device, precision and a hash of every instance's
+// (M, L, m, N).
+std::string batch_tune_key(const bl_batch_s* b) {
+    uint64_t h = 1469598103934665603ull;   // FNV-1a
+    auto mix = [&](int64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= uint64_t((v >> (8 * k)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    for (const InstDesc& d : b->h_desc) {
+        mix(d.M);
+        mix(d.L);
+        mix(d.m);
+    }
+    for (int i = 0; i < b->count; ++i) mix(b->h_node_off[i + 1] - b->h_node_off[i]);
+    char buf[32];
+    std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
+    return "batch|" + tune_device_tag(b->device) + "|n" + std::to_string(b->count) + "|" +
+           (b->prec == BL_F32 ? "f32" : b->prec == BL_F32C ? "f32c" : "f32d") + "|" + buf;
+}
+
 bl_status autotune_tile(bl_batch_s* b, const float* x) {
+    const std::string key = batch_tune_key(b);
+    std::vector<int> cached;
+    if (tune_lookup(key, &cached) && cached.size() == 1) {
+        b->tile = cached[0];
+        b->tuned = true;
+        return BL_OK;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     CxF* fdummy = nullptr;
     bl_status st = balloc(&fdummy, sizeof(CxF) * b->total_N);
@@ -908,6 +942,7 @@ bl_status autotune_tile(bl_batch_s* b, const float* x) {
     if (st != BL_OK) return st;
     b->tile = best_tile;
     b->tuned = true;
+    tune_store(key, std::vector<int>{best_tile});
     return BL_OK;
 }
 
@@ -1133,8 +1168,9 @@ bl_status bl_batch_set_nodes(bl_batch b, const void* x_dev) {
     b->have_nodes = false;
     drop_graph(b);
     const float* x = static_cast<const float*>(x_dev);
-    if (!b->tuned && b->total_N > 0) {
-        // Autotune the tile edge: bin with each candidate and time the short sums alone.
+    if (!b->tuned && b->total_N > 0 && tuning_enabled()) {
+        // Autotune the tile edge (or read it from the tuning cache): bin with each
+        // candidate and time the short sums alone.
         bl_status st = autotune_tile(b, x);
         if (st != BL_OK) return st;
     }

@@ -33,6 +33,9 @@ const std::string& last_error();
     } while (0)
 
 constexpr int kMaxStages = 16;
+constexpr int kCovMax = 4;                    // covering boxes per coordinate in the merge table
+constexpr int kCovRow = 2 + 2 * kCovMax;      // tile, count, (tile offset, box position) pairs
+constexpr int kNbR = 2;                       // largest tile offset of a covering box per dimension
 constexpr int kMinM = 2;    // truncation range of the compiled short-sum kernels
 constexpr int kMaxM = 8;
 constexpr int kPolyCoef = 12;   // coefficients of the float weight polynomials (degree 11)
@@ -180,6 +183,11 @@ struct Plan {
     int32_t* d_tile_cursor = nullptr;
     int32_t* d_chunk_offset = nullptr;
     void* d_scan = nullptr;        // block sums of the tile scans (tile_scan_scratch_bytes)
+    // Adjoint merge tables: per grid coordinate (shared by the dimensions) its tile and the
+    // (tile offset, box position) pairs of the boxes that cover it (kCovRow ints, up to
+    // kCovMax pairs with offsets within kNbR; null otherwise), and one reach flag per tile.
+    int* d_cov = nullptr;
+    unsigned char* d_reach = nullptr;
     int4* d_chunks = nullptr;      // {tile, start, count, 0}
     int64_t chunk_alloc = 0;
     int64_t nchunks = 0;
@@ -285,6 +293,10 @@ bl_status tune_fft_lines(Plan& p, void* buf_in, void* buf_out);
 // autotune.cpp: FFT lines per workgroup at plan creation (cached), and the cache of the
 // short-sum tile edge and chunk capacity measured at the first large node binding.
 constexpr int64_t kTuneMinNodes = int64_t(1) << 16;
+bool tuning_enabled();
+bool tune_lookup(const std::string& key, std::vector<int>* vals);
+void tune_store(const std::string& key, const std::vector<int>& vals);
+std::string tune_device_tag(int device);   // architecture and compute-unit count
 bl_status autotune_fft(Plan& p);
 bool tile_tuning_wanted(const Plan& p, int64_t N);
 bool tile_cache_lookup(const Plan& p, int density, int cluster, int* T, int* cap);

@@ -20,6 +20,7 @@
 //    in double and rounds once, when the grid of samples (or the output band) is stored.
 //  * L that is not a power of two (or a d = 1 line longer than the LDS pass takes) runs
 //    the chirp-z passes of czt.hip instead, with the same layouts and factors.
+#include <cstdio>
 #include <cstdlib>
 
 #include "blnfft_internal.h"
@@ -537,6 +538,9 @@ bl_status tune_fft_lines(Plan& p, void* buf_in, void* buf_out) {
                 for (int lines = 1; lines <= 64; lines *= 2) {
                     const double ms = dir == 0 ? time_pass<+1>(p, a, t, lines, radix, 5, e0, e1)
                                                : time_pass<-1>(p, a, t, lines, radix, 5, e0, e1);
+                    if (ms > 0.0 && std::getenv("BL_TUNE_VERBOSE"))
+                        std::fprintf(stderr, "blnfft tune fft: %s axis %d lines=%d radix=%d: %.2f us\n",
+                                     dir == 0 ? "forward" : "adjoint", axis, lines, radix, ms * 1e3);
                     if (ms > 0.0 && (best == 0 || ms < best_ms)) {
                         best = lines;
                         best_radix = p.czt.on ? 0 : radix;

@@ -326,8 +326,10 @@ constexpr size_t rows_lds_bytes() {
            sizeof(int) * (48 + rows_batch<R>()) + sizeof(float) * kMaxM * kPolyCoef;
 }
 
-template <typename R, int M2, int METHOD, bool EXACT>
-__global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
+// RPL box rows per lane: 4 (256 threads, waves of 8 rows) or 8 (128 threads, waves of 16
+// rows: more FMAs per broadcast LDS load, fewer waves visiting each node).
+template <typename R, int M2, int METHOD, bool EXACT, int RPL = 4>
+__global__ void __launch_bounds__(1024 / RPL) k_spread_rows(SpreadArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int m = M2 / 2;
     constexpr int NB = rows_batch<R>();
@@ -350,14 +352,15 @@ __global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
     if constexpr (std::is_same<R, float>::value) {
         for (int e = tid; e < m * kPolyCoef; e += blockDim.x) coef[e] = a.poly[e];
     }
+    constexpr int RW = 2 * RPL;   // box rows per wave
     const int lane = tid & 63, wv = tid >> 6;
     const int c1 = lane & 31;
-    const int cb = 8 * wv + 4 * (lane >> 5);
-    // tile rows whose nodes reach box rows [8 wv, 8 wv + 8)
-    const int rlo = max(0, 8 * wv - M2 + 1), rhi = min(T0 - 1, 8 * wv + 7);
-    Cx<R> acc[4];
+    const int cb = RW * wv + RPL * (lane >> 5);
+    // tile rows whose nodes reach box rows [RW wv, RW wv + RW)
+    const int rlo = max(0, RW * wv - M2 + 1), rhi = min(T0 - 1, RW * wv + RW - 1);
+    Cx<R> acc[RPL];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] = Cx<R>{R(0), R(0)};
+    for (int k = 0; k < RPL; ++k) acc[k] = Cx<R>{R(0), R(0)};
 
     const R* __restrict__ xs = static_cast<const R*>(a.xs);
     const Cx<R>* __restrict__ g = static_cast<const Cx<R>*>(a.g);
@@ -421,9 +424,9 @@ __global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
 #pragma unroll 2
         for (int j = js; j < je; j += VEC) {
             const vec_t wl = *reinterpret_cast<const vec_t*>(w1p + j);
-            vec_t w0[4];
+            vec_t w0[RPL];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) w0[k] = *reinterpret_cast<const vec_t*>(w0p + k * P + j);
+            for (int k = 0; k < RPL; ++k) w0[k] = *reinterpret_cast<const vec_t*>(w0p + k * P + j);
             Cx<R> gq[VEC];
 #pragma unroll
             for (int q = 0; q < VEC; ++q) gq[q] = gv[j + q];
@@ -431,7 +434,7 @@ __global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
             for (int q = 0; q < VEC; ++q) {
                 const R are = wl[q] * gq[q].re, aim = wl[q] * gq[q].im;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < RPL; ++k) {
                     acc[k].re = dev_fma(w0[k][q], are, acc[k].re);
                     acc[k].im = dev_fma(w0[k][q], aim, acc[k].im);
                 }
@@ -442,7 +445,7 @@ __global__ void __launch_bounds__(256) k_spread_rows(SpreadArgs a) {
     if (c1 >= W[1]) return;
     const int ci = xcd_block(int(blockIdx.x), int(gridDim.x));
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < RPL; ++k) {
         const int c0 = cb + k;
         if (c0 < W[0]) box_store<R>(a, ci, c0 * W[1] + c1, acc[k]);
     }
@@ -822,7 +825,19 @@ KFn spread_os_m(int m) {
 }
 
 template <typename R, int METHOD, bool EXACT>
-KFn spread_rows_m(int m) {
+KFn spread_rows_m(int m, int rpl) {
+    if (rpl == 8) {
+        switch (m) {
+            case 2: return k_spread_rows<R, 4, METHOD, EXACT, 8>;
+            case 3: return k_spread_rows<R, 6, METHOD, EXACT, 8>;
+            case 4: return k_spread_rows<R, 8, METHOD, EXACT, 8>;
+            case 5: return k_spread_rows<R, 10, METHOD, EXACT, 8>;
+            case 6: return k_spread_rows<R, 12, METHOD, EXACT, 8>;
+            case 7: return k_spread_rows<R, 14, METHOD, EXACT, 8>;
+            case 8: return k_spread_rows<R, 16, METHOD, EXACT, 8>;
+            default: return nullptr;
+        }
+    }
     switch (m) {
         case 2: return k_spread_rows<R, 4, METHOD, EXACT>;
         case 3: return k_spread_rows<R, 6, METHOD, EXACT>;
@@ -878,6 +893,10 @@ struct MergeArgs {
     void* grid;
     const int32_t* tile_count;   // nodes per tile
     const int32_t* chunk_off;    // first chunk of each tile
+    const int* cov;              // coverage table, kCovRow ints per coordinate (or null):
+                                 // tile of p, count, (tile offset, box position) pairs
+    unsigned char* reach;        // per tile: some non-empty box covers it
+    int periodic;                // tile offsets wrap (Algorithm 2.1)
     int64_t box_vol, n;
     int L, m, cap;
     int tile[3], tpd[3], W[3];
@@ -902,23 +921,22 @@ __device__ __forceinline__ void covering(int p, int L, int T, int tpd, int m, in
 }
 
 // One thread per grid point: the sum of the covering boxes' entries, over tiles in row-major
-// order (and s), and over each tile's chunks in order.  Every grid point is written.
+// order (and s), and over each tile's chunks in order.  Every grid point is written.  This general form derives the covering tiles by division;
+// k_box_merge_tiles below reads them from per-coordinate tables and is used whenever those
+// fit.
 template <typename R, int D, int METHOD>
 __global__ void __launch_bounds__(256) k_box_merge(MergeArgs a) {
-    const int64_t gi = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (gi >= a.n) return;
     int p[3] = {0, 0, 0};
-    {
-        int64_t r = gi;
+    p[D - 1] = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (p[D - 1] >= a.L) return;
+    if (D >= 2) p[D - 2] = int(blockIdx.y);
+    if (D == 3) p[0] = int(blockIdx.z);
+    int64_t gi = 0;
 #pragma unroll
-        for (int t = D - 1; t >= 0; --t) {
-            p[t] = int(r % a.L);
-            r /= a.L;
-        }
-    }
+    for (int t = 0; t < D; ++t) gi = gi * a.L + p[t];
     const Cx<R>* __restrict__ boxes = static_cast<const Cx<R>*>(a.boxes);
     R re = R(0), im = R(0);
-    auto add_tile = [&](int tile, int e) {
+    auto add_tile = [&](int tile, int e) {   // the tile's chunks in order
         const int cnt = a.tile_count[tile];
         if (cnt == 0) return;
         const int nch = (cnt + a.cap - 1) / a.cap;
@@ -949,11 +967,166 @@ __global__ void __launch_bounds__(256) k_box_merge(MergeArgs a) {
     static_cast<Cx<R>*>(a.grid)[gi] = Cx<R>{re, im};
 }
 
+// Per-tile flag: does the box of some non-empty tile cover a point of this tile?  Cleared,
+// then marked from the non-empty tiles: tile t spans box coordinates t T - m + 1 ...
+// t T + T + m - 2 per dimension (wrapped for the periodic sums), and every tile holding
+// one of them is marked (the same value from every writer).  Launched over the tiles as a
+// 3-D grid (last dimension in x), so no index is divided.
+constexpr int kReachList = 8;
+__global__ void k_reach_clear(unsigned char* reach, int64_t ntiles) {
+    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (t < ntiles) reach[t] = 0;
+}
+
+template <int D, int METHOD>
+__global__ void __launch_bounds__(256) k_reach_mark(MergeArgs a) {
+    int tc[3] = {0, 0, 0};
+    tc[D - 1] = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (tc[D - 1] >= a.tpd[D - 1]) return;
+    if (D >= 2) tc[D - 2] = int(blockIdx.y);
+    if (D == 3) tc[0] = int(blockIdx.z);
+    int t = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) t = t * a.tpd[k] + tc[k];
+    if (a.tile_count[t] == 0) return;
+    int list[3][kReachList], n[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int T = a.tile[k];
+        const int c0 = tc[k] * T - a.m + 1, c1 = tc[k] * T + T + a.m - 2;
+        int last = -1;
+        for (int c = c0; c <= c1; ++c) {
+            int q = c;
+            if (METHOD == 1) q = ((q % a.L) + a.L) % a.L;
+            else if (q < 0 || q >= a.L) continue;
+            const int tt = q / T;
+            if (tt == last) continue;
+            last = tt;
+            bool seen = false;
+            for (int e = 0; e < n[k]; ++e) seen = seen || list[k][e] == tt;
+            if (!seen && n[k] < kReachList) list[k][n[k]++] = tt;
+        }
+    }
+    if constexpr (D == 1) {
+        for (int i = 0; i < n[0]; ++i) a.reach[list[0][i]] = 1;
+    } else if constexpr (D == 2) {
+        for (int i = 0; i < n[0]; ++i)
+            for (int j = 0; j < n[1]; ++j) a.reach[list[0][i] * a.tpd[1] + list[1][j]] = 1;
+    } else {
+        for (int i = 0; i < n[0]; ++i)
+            for (int j = 0; j < n[1]; ++j)
+                for (int k = 0; k < n[2]; ++k) a.reach[(list[0][i] * a.tpd[1] + list[1][j]) * a.tpd[2] + list[2][k]] = 1;
+    }
+}
+
+// Zero fill of the spreading grid (16-byte stores; n16 of them, then the tail of nbytes).
+__global__ void __launch_bounds__(256) k_grid_zero(uint4* g, int64_t n16) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n16) g[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// The merge, one workgroup per tile, after the grid has been zero-filled: a tile that no
+// non-empty box reaches keeps its zeros.  Otherwise the workgroup first stages, for every
+// neighbour offset (dt_0, ..., dt_{d-1}) in [-kNbR, kNbR]^d, the first chunk box of that
+// neighbour and its chunk count (-1 for an empty or absent tile); then every point of the
+// tile is the sum over the (offset, box position) pairs of its coordinates' coverage rows,
+// in row-major order of the pairs and chunk order within a tile (each chunk-box entry is
+// read exactly once, by the one grid point it covers).
+template <typename R, int D>
+__global__ void __launch_bounds__(256) k_box_merge_tiles(MergeArgs a) {
+    constexpr int NB = 2 * kNbR + 1;
+    constexpr int NBV = D == 1 ? NB : D == 2 ? NB * NB : NB * NB * NB;
+    __shared__ long long nb[NBV];    // first box of the neighbour tile (-1: none)
+    __shared__ int nbc[NBV];         // its chunk count
+    const int t = int(blockIdx.x);
+    if (!a.reach[t]) return;
+    int tc[3] = {0, 0, 0}, n0[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+    {
+        int r = t;
+#pragma unroll
+        for (int k = D - 1; k >= 0; --k) {
+            tc[k] = r % a.tpd[k];
+            r /= a.tpd[k];
+            n0[k] = tc[k] * a.tile[k];
+            ext[k] = min(a.tile[k], a.L - n0[k]);
+        }
+    }
+    for (int q = threadIdx.x; q < NBV; q += blockDim.x) {
+        int rem = q, tt = 0;
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int stride = D - 1 - k == 2 ? NB * NB : D - 1 - k == 1 ? NB : 1;
+            const int dk = rem / stride - kNbR;
+            rem %= stride;
+            int u = tc[k] + dk;
+            if (a.periodic) u = ((u % a.tpd[k]) + a.tpd[k]) % a.tpd[k];
+            else ok = ok && u >= 0 && u < a.tpd[k];
+            tt = tt * a.tpd[k] + (u < 0 ? 0 : u);
+        }
+        const int cnt = ok ? a.tile_count[tt] : 0;
+        nb[q] = cnt > 0 ? (long long)a.chunk_off[tt] * a.box_vol : -1;
+        nbc[q] = (cnt + a.cap - 1) / a.cap;
+    }
+    __syncthreads();
+    const Cx<R>* __restrict__ boxes = static_cast<const Cx<R>*>(a.boxes);
+    Cx<R>* __restrict__ grid = static_cast<Cx<R>*>(a.grid);
+    const int vol = ext[0] * ext[1] * ext[2];
+    for (int e = threadIdx.x; e < vol; e += blockDim.x) {
+        int p[3] = {0, 0, 0};
+        {
+            int r = e;
+#pragma unroll
+            for (int k = D - 1; k >= 0; --k) {
+                p[k] = n0[k] + r % ext[k];
+                r /= ext[k];
+            }
+        }
+        const int* r0 = a.cov + p[0] * kCovRow;
+        const int* r1 = a.cov + p[D >= 2 ? 1 : 0] * kCovRow;
+        const int* r2 = a.cov + p[D == 3 ? 2 : 0] * kCovRow;
+        const int n0c = r0[1], n1c = D >= 2 ? r1[1] : 1, n2c = D == 3 ? r2[1] : 1;
+        R re = R(0), im = R(0);
+        for (int i = 0; i < n0c; ++i) {
+            const int o0 = r0[2 + 2 * i] + kNbR, c0 = r0[3 + 2 * i];
+            for (int j = 0; j < n1c; ++j) {
+                const int o1 = D >= 2 ? r1[2 + 2 * j] + kNbR : 0, c1 = D >= 2 ? r1[3 + 2 * j] : 0;
+#pragma unroll 4
+                for (int k = 0; k < n2c; ++k) {
+                    const int o2 = D == 3 ? r2[2 + 2 * k] + kNbR : 0, c2 = D == 3 ? r2[3 + 2 * k] : 0;
+                    const int slot = D == 1 ? o0 : D == 2 ? o0 * NB + o1 : (o0 * NB + o1) * NB + o2;
+                    const int be = D == 1 ? c0 : D == 2 ? c0 * a.W[1] + c1 : (c0 * a.W[1] + c1) * a.W[2] + c2;
+                    const long long base = nb[slot];
+                    if (base >= 0) {
+                        const int nch = nbc[slot];
+                        for (int c = 0; c < nch; ++c) {   // the tile's chunks in order
+                            const Cx<R> v = boxes[base + int64_t(c) * a.box_vol + be];
+                            re += v.re;
+                            im += v.im;
+                        }
+                    }
+                }
+            }
+        }
+        int64_t gi = p[0];
+        if (D >= 2) gi = gi * a.L + p[1];
+        if (D == 3) gi = gi * a.L + p[2];
+        grid[gi] = Cx<R>{re, im};
+    }
+}
+
 template <typename R, int METHOD>
 KFnM merge_d(int d) {
     if (d == 1) return k_box_merge<R, 1, METHOD>;
     if (d == 2) return k_box_merge<R, 2, METHOD>;
     return k_box_merge<R, 3, METHOD>;
+}
+
+template <typename R>
+KFnM merge_tiles_d(int d) {
+    if (d == 1) return k_box_merge_tiles<R, 1>;
+    if (d == 2) return k_box_merge_tiles<R, 2>;
+    return k_box_merge_tiles<R, 3>;
 }
 
 SpreadArgs make_args(const Plan& p) {
@@ -1009,10 +1182,34 @@ bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes) {
         ma.tpd[t] = p.tiles_per_dim[t];
         ma.W[t] = p.tile[t] + 2 * p.m - 1;
     }
+    ma.cov = p.d_cov;
+    ma.reach = p.d_reach;
+    ma.periodic = p.method == BL_NFFT ? 1 : 0;
     auto merge = [&]() -> bl_status {
-        const KFnM mf = p.prec == BL_F64 ? (p.method == BL_NFFT ? merge_d<double, 1>(p.d) : merge_d<double, 0>(p.d))
-                                         : (p.method == BL_NFFT ? merge_d<float, 1>(p.d) : merge_d<float, 0>(p.d));
-        hipLaunchKernelGGL(mf, dim3(unsigned((ma.n + 255) / 256)), dim3(256), 0, p.stream, ma);
+        KFnM mf;
+        if (p.d_cov) {
+            hipLaunchKernelGGL(k_reach_clear, dim3(unsigned((p.ntiles + 255) / 256)), dim3(256), 0, p.stream,
+                               p.d_reach, p.ntiles);
+            const dim3 tg(unsigned((p.tiles_per_dim[p.d - 1] + 255) / 256), p.d >= 2 ? unsigned(p.tiles_per_dim[p.d - 2]) : 1u,
+                          p.d == 3 ? unsigned(p.tiles_per_dim[0]) : 1u);
+            KFnM rf;
+            if (p.method == BL_NFFT) rf = p.d == 1 ? k_reach_mark<1, 1> : p.d == 2 ? k_reach_mark<2, 1> : k_reach_mark<3, 1>;
+            else rf = p.d == 1 ? k_reach_mark<1, 0> : p.d == 2 ? k_reach_mark<2, 0> : k_reach_mark<3, 0>;
+            hipLaunchKernelGGL(rf, tg, dim3(256), 0, p.stream, ma);
+            const int64_t bytes = p.grid_elems() * int64_t(p.cplx_size());   // a multiple of 16 (L even)
+            hipLaunchKernelGGL(k_grid_zero, dim3(unsigned((bytes / 16 + 255) / 256)), dim3(256), 0, p.stream,
+                               static_cast<uint4*>(grid), bytes / 16);
+            BL_HIP(hipGetLastError());
+            mf = p.prec == BL_F64 ? merge_tiles_d<double>(p.d) : merge_tiles_d<float>(p.d);
+            hipLaunchKernelGGL(mf, dim3(unsigned(p.ntiles)), dim3(256), 0, p.stream, ma);
+            BL_HIP(hipGetLastError());
+            return BL_OK;
+        } else {
+            mf = p.prec == BL_F64 ? (p.method == BL_NFFT ? merge_d<double, 1>(p.d) : merge_d<double, 0>(p.d))
+                                  : (p.method == BL_NFFT ? merge_d<float, 1>(p.d) : merge_d<float, 0>(p.d));
+        }
+        const dim3 g(unsigned((p.L + 255) / 256), p.d >= 2 ? unsigned(p.L) : 1u, p.d == 3 ? unsigned(p.L) : 1u);
+        hipLaunchKernelGGL(mf, g, dim3(256), 0, p.stream, ma);
         BL_HIP(hipGetLastError());
         return BL_OK;
     };
@@ -1036,13 +1233,16 @@ bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes) {
     const bool use_os = !use_rows && !use_rows3 && box <= int64_t(kp) * kOsThreads && os_lds <= 160 * 1024 &&
                         std::getenv("BL_SPREAD_ATOMIC") == nullptr;
     KFn fn;
+    // d = 2 row kernel: box rows per lane (BL_SPREAD_RPL overrides)
+    int rpl = 8;
+    if (const char* e = std::getenv("BL_SPREAD_RPL")) rpl = std::atoi(e) == 4 ? 4 : 8;
     // Double row kernels with closed-form weights are separate instantiations, so that the
     // polynomial ones are not register-sized for them.
     const bool exact = p.prec == BL_F64 && !p.use_poly64;
     if (use_rows) {
-        if (p.prec != BL_F64) fn = p.method == BL_NFFT ? spread_rows_m<float, 1, false>(p.m) : spread_rows_m<float, 0, false>(p.m);
-        else if (exact) fn = p.method == BL_NFFT ? spread_rows_m<double, 1, true>(p.m) : spread_rows_m<double, 0, true>(p.m);
-        else fn = p.method == BL_NFFT ? spread_rows_m<double, 1, false>(p.m) : spread_rows_m<double, 0, false>(p.m);
+        if (p.prec != BL_F64) fn = p.method == BL_NFFT ? spread_rows_m<float, 1, false>(p.m, rpl) : spread_rows_m<float, 0, false>(p.m, rpl);
+        else if (exact) fn = p.method == BL_NFFT ? spread_rows_m<double, 1, true>(p.m, rpl) : spread_rows_m<double, 0, true>(p.m, rpl);
+        else fn = p.method == BL_NFFT ? spread_rows_m<double, 1, false>(p.m, rpl) : spread_rows_m<double, 0, false>(p.m, rpl);
     } else if (use_rows3) {
         if (p.prec != BL_F64) fn = p.method == BL_NFFT ? spread_rows3_m<float, 1, false>(p.m) : spread_rows3_m<float, 0, false>(p.m);
         else if (exact) fn = p.method == BL_NFFT ? spread_rows3_m<double, 1, true>(p.m) : spread_rows3_m<double, 0, true>(p.m);
@@ -1063,7 +1263,8 @@ bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes) {
                        : use_os ? os_lds : box_bytes(p) + 16 + sizeof(float) * kMaxM * kPolyCoef;
     if (lds > 64 * 1024)
         BL_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-    hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(256), lds, p.stream, a);
+    const unsigned threads = use_rows ? unsigned(1024 / rpl) : 256u;
+    hipLaunchKernelGGL(fn, dim3(unsigned(p.nchunks)), dim3(threads), lds, p.stream, a);
     BL_HIP(hipGetLastError());
     return merge();
 }

@@ -28,8 +28,9 @@ def _loss(plan, fhat, x, y):
     return (f - y).abs().pow(2).sum()
 
 
-@pytest.mark.parametrize("d,M,L,m,N", [(1, 64, 128, 5, 800), (2, 32, 64, 4, 1500), (3, 16, 32, 3, 700)])
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("d,M,L,m,N", [(1, 64, 128, 5, 800), (2, 32, 64, 4, 1500), (3, 16, 32, 3, 700),
+                                       (2, 40, 96, 5, 1200)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32c", "f32d"])
 def test_autograd_matches_oracle_gradients(d, M, L, m, N, prec):
     p = W.custom_problem(d, M, L, m, N, seed=500 + d, precision="f32" if prec != "f64" else "f64",
                          with_targets=True)

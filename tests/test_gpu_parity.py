@@ -56,6 +56,8 @@ SMALL = [
     (2, 48, 64, 8, 2000),
     (3, 16, 32, 4, 3000),
     (3, 24, 32, 2, 1500),
+    (2, 64, 128, 7, 3000),        # m = 7
+    (3, 16, 32, 7, 1500),
     (1, 2048, 4096, 6, 3000),     # 1-D lines above 2048 points: radix-16 passes
     (1, 4096, 8192, 8, 2000),     # the longest supported line
     (2, 512, 2048, 4, 3000),
@@ -204,6 +206,33 @@ def test_d3_ones_against_the_dirichlet_product(prec):
     assert err <= bound
 
 
+def test_failed_allocation_is_reported_as_enomem(monkeypatch):
+    """Every device allocation of plan creation and node binding goes through one checked
+    path: a refused allocation (forced from the host by BL_TEST_FAIL_ALLOC) comes back as
+    BL_ENOMEM with a message, leaves no plan behind, and the next call succeeds."""
+    torch = torch_mod()
+    from paper_2502_07155_amd import BLNFFTError, BatchPlan, Plan
+    monkeypatch.setenv("BL_TEST_FAIL_ALLOC", "1")
+    with pytest.raises(BLNFFTError) as ei:
+        Plan(2, 32, 64, 4, precision="f32")
+    assert ei.value.status == 3 and "BL_TEST_FAIL_ALLOC" in str(ei.value)
+    with pytest.raises(BLNFFTError) as ei:
+        BatchPlan([32, 64], [64, 128], [4, 5], [100, 200], precision="f32")
+    assert ei.value.status == 3
+    monkeypatch.delenv("BL_TEST_FAIL_ALLOC")
+    plan = Plan(2, 32, 64, 4, precision="f32")
+    monkeypatch.setenv("BL_TEST_FAIL_ALLOC", "1")
+    with pytest.raises(BLNFFTError) as ei:
+        plan.set_nodes(torch.zeros((50, 2), dtype=torch.float32, device="cuda"))
+    assert ei.value.status == 3
+    monkeypatch.delenv("BL_TEST_FAIL_ALLOC")
+    p = W.custom_problem(2, 32, 64, 4, 500, seed=88, precision="f32")
+    plan.set_nodes(dev_real(p.x, "f32"))
+    f = host(plan.forward(dev_cplx(p.fhat, "f32")))
+    assert O.rel_err_inf(f, O.forward_shannon(p.fhat, p.x, 64, 4)) <= 1e-5
+    plan.close()
+
+
 def test_edge_nodes_grid_points_and_bounds():
     """Nodes on grid points (L x integer), at -1/2 exactly, just below 1/2, and clustered
     into one tile far beyond one work chunk."""
@@ -314,8 +343,9 @@ def test_adjoint_spread_kernels(d, M, L, m, N, tile, prec, kernel, monkeypatch):
 
 
 @pytest.mark.parametrize("d,M,L,m,N", [(1, 64, 128, 5, 1500), (2, 32, 64, 4, 3000),
-                                       (3, 16, 32, 3, 1500), (2, 256, 512, 6, 20000)])
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+                                       (3, 16, 32, 3, 1500), (2, 256, 512, 6, 20000),
+                                       (2, 60, 120, 7, 2000)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32c", "f32d"])
 def test_grad_x_matches_oracle(d, M, L, m, N, prec):
     p = W.custom_problem(d, M, L, m, N, seed=400 + d + m, precision="f32" if prec != "f64" else "f64",
                          with_targets=True)
