@@ -451,6 +451,208 @@ __global__ void __launch_bounds__(1024 / RPL) k_spread_rows(SpreadArgs a) {
     }
 }
 
+// d = 2 spreading on the matrix cores (float).  For one batch of a chunk's nodes the box
+// is B[r][c] = sum_j (g_j w0_j(r)) w1_j(c), the product of a (rows x nodes) and a (nodes x
+// columns) matrix that are mostly zero.  The box (at most 32 x 32) is covered by two bands
+// of 16 rows, [0, 16) and [S, S + 16) with S = W0 - 16 (band 1 alone when W0 <= 16), and
+// two blocks of 16 columns; each band-block product is a chain of 16x16x4 FP32 MFMAs, four
+// nodes per instruction.  Band 1 takes the nodes whose rows reach row 16; rows below 16 of
+// a node that starts below row S are band 0's (masked out of band 1), and band 0 takes no
+// node that starts at row S or later.  The batch is sorted by cell, so band 0's nodes are a
+// prefix of the batch and band 1's a suffix.  Waves take the (band, group of 16 nodes)
+// items in turn; at the end the four waves' accumulators are summed through LDS in a fixed
+// order (waves 0..3, band 0 then band 1), so a box does not depend on timing.
+//
+// One workgroup per chunk.  A staging thread owns one column of one weight table (node jj,
+// dimension dim), so it clears the entries it wrote for the previous batch before writing
+// the next: the tables are cleared in full only once.  The loads run one batch ahead
+// (coordinates and node indices of batch b + 1, values of batch b in flight while batch
+// b - 1 is on the matrix cores), in straight-line code and in two slots that take turns,
+// so that nothing waits for a load before its use.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaBatch = 128;                 // nodes per batch (two staging threads each)
+constexpr int kMfmaPitch = kMfmaBatch + 4;      // LDS row pitch of the weight tables
+constexpr int kMfmaFar = 1 << 20;               // first row of the empty slots past a batch
+constexpr size_t mfma2_lds_bytes() {
+    return sizeof(float) * 64 * kMfmaPitch + sizeof(Cx<float>) * kMfmaBatch + sizeof(int) * kMfmaBatch +
+           sizeof(float) * kMaxM * kPolyCoef;
+}
+
+// One item: 16 nodes from j0 into the band's accumulators acc[column block][re, im].
+template <int BAND>
+__device__ __forceinline__ void mfma2_item(const float* ws, const Cx<float>* gv, const int* rrow, int j0,
+                                           int S, mfma_f4 (&acc)[2][2]) {
+    constexpr int P = kMfmaPitch;
+    const int lane = threadIdx.x & 63, kq = lane >> 4, i = lane & 15;
+    const int jb = j0 + 4 * kq;            // this lane's four nodes: k slot kq of four MFMAs
+    const int rho = BAND ? S + i : i;      // box row of the A operand (row i of the band)
+    const mfma_f4 av = *reinterpret_cast<const mfma_f4*>(ws + rho * P + jb);
+    const int4 rr = *reinterpret_cast<const int4*>(rrow + jb);
+    const mfma_f4 b0 = *reinterpret_cast<const mfma_f4*>(ws + (32 + i) * P + jb);
+    const mfma_f4 b1 = *reinterpret_cast<const mfma_f4*>(ws + (48 + i) * P + jb);
+    const mfma_f4 gA = *reinterpret_cast<const mfma_f4*>(gv + jb);
+    const mfma_f4 gB = *reinterpret_cast<const mfma_f4*>(gv + jb + 2);
+    const float gre[4] = {gA[0], gA[2], gB[0], gB[2]};
+    const float gim[4] = {gA[1], gA[3], gB[1], gB[3]};
+    const int rq[4] = {rr.x, rr.y, rr.z, rr.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool keep = BAND ? (rho >= 16 || rq[q] >= S) : (rq[q] < S);
+        const float aq = keep ? av[q] : 0.0f;
+        const float are = aq * gre[q], aim = aq * gim[q];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(are, b0[q], acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, b0[q], acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(are, b1[q], acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim, b1[q], acc[1][1], 0, 0, 0);
+    }
+}
+
+template <int M2>
+__global__ void __launch_bounds__(256) k_spread_mfma2(SpreadArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int NB = kMfmaBatch;
+    constexpr int P = kMfmaPitch;
+    // ws rows 0..31: first-dimension weight of each batch node at its box row; rows 32..63:
+    // last-dimension weight at its box column (zero outside the node's window)
+    float* ws = reinterpret_cast<float*>(smem_raw);
+    Cx<float>* gv = reinterpret_cast<Cx<float>*>(ws + 64 * P);   // [NB] node values
+    int* rrow = reinterpret_cast<int*>(gv + NB);                   // [NB] first box row of each node
+    float* coef = reinterpret_cast<float*>(rrow + NB);
+    __shared__ int cnt[2][2];   // per staging wave: batch nodes starting below S, below r1lo
+
+    const int ci = xcd_block(int(blockIdx.x), int(gridDim.x));
+    const int4 ch = a.chunks[ci];
+    const int L = a.L;
+    const int tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index (uniform)
+    int n0[3] = {0, 0, 0}, W[3] = {1, 1, 1};
+    tile_geometry<2>(ch, a.tpd, a.tile, M2, n0, W);
+    for (int e = tid; e < (M2 / 2) * kPolyCoef; e += blockDim.x) coef[e] = a.poly[e];
+    {
+        mfma_f4* z = reinterpret_cast<mfma_f4*>(ws);
+        for (int e = tid; e < 64 * P / 4; e += blockDim.x) z[e] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    const int S = W[0] > 16 ? W[0] - 16 : 0;
+    const int r1lo = min(S, max(0, 17 - M2));   // first box row from which a window reaches row 16
+    mfma_f4 acc0[2][2], acc1[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            acc0[b][c] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+            acc1[b][c] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+
+    const float* __restrict__ xs = static_cast<const float*>(a.xs);
+    const Cx<float>* __restrict__ g = static_cast<const Cx<float>*>(a.g);
+    const int jj = tid & (NB - 1), dim = tid >> 7;   // staging: node jj, dimension dim
+    const int nbatch = (ch.z + NB - 1) / NB;
+    // node of slot jj in batch b (slots past the chunk read its last node and are not used)
+    auto node = [&](int b) { return int64_t(ch.y) + min(b * NB + jj, ch.z - 1); };
+    struct Slot {
+        float x;
+        int p;
+        Cx<float> gq;
+    };
+    Slot sa, sb;
+    sa.x = xs[node(0) * 2 + dim];
+    sa.p = a.perm[node(0)];
+    sb.x = xs[node(1) * 2 + dim];
+    sb.p = a.perm[node(1)];
+    sa.gq = g[sa.p];
+    int prev_r = -1;   // first table row this thread wrote for the previous batch (-1: none)
+    // batch b from slot `use` (coordinate and value loaded); then the value of batch b + 1
+    // into `other` and the coordinate and index of batch b + 2 into `use`
+    auto batch = [&](int b, Slot& use, Slot& other) {
+        const int nb = min(NB, ch.z - b * NB);
+        __syncthreads();   // tables cleared / previous batch consumed
+        int r = kMfmaFar;
+        {
+            float* wd = ws + dim * 32 * P + jj;   // this thread's column
+            if (prev_r >= 0) {
+#pragma unroll
+                for (int o = 0; o < M2; ++o) wd[(prev_r + o) * P] = 0.0f;
+            }
+            prev_r = -1;
+            if (jj < nb) {
+                int nc;
+                float th;
+                cell_of<float>(use.x, L, nc, th);
+                r = nc + L / 2 - n0[dim];
+                float w[1][M2];
+                weights_poly<1, M2, kPolyCoef>(&th, coef, w, a.edge_k);
+#pragma unroll
+                for (int o = 0; o < M2; ++o) wd[(r + o) * P] = w[0][o];
+                prev_r = r;
+            }
+        }
+        if (dim == 0) {
+            gv[jj] = jj < nb ? use.gq : Cx<float>{0.0f, 0.0f};   // zero past the batch
+            rrow[jj] = r;
+            // the batch is sorted by box row: the counts below a row are prefix lengths
+            const int below_s = __popcll(__ballot(r < S));
+            const int below_r1 = __popcll(__ballot(r < r1lo));
+            if ((tid & 63) == 0) {
+                cnt[wv][0] = below_s;
+                cnt[wv][1] = below_r1;
+            }
+        }
+        other.gq = g[other.p];
+        use.x = xs[node(b + 2) * 2 + dim];
+        use.p = a.perm[node(b + 2)];
+        __syncthreads();
+        const int n0g = (cnt[0][0] + cnt[1][0] + 15) >> 4;   // band 0: nodes [0, #rows < S)
+        const int s1 = (cnt[0][1] + cnt[1][1]) & ~15;         // band 1: nodes [s1, nb)
+        const int n1g = (nb - s1 + 15) >> 4;
+        for (int it = wv; it < n0g; it += 4) mfma2_item<0>(ws, gv, rrow, 16 * it, S, acc0);
+        for (int it = n0g + ((wv - n0g) % 4 + 4) % 4; it < n0g + n1g; it += 4)
+            mfma2_item<1>(ws, gv, rrow, s1 + 16 * (it - n0g), S, acc1);
+    };
+    for (int b = 0; b < nbatch; b += 2) {
+        batch(b, sa, sb);
+        if (b + 1 < nbatch) batch(b + 1, sb, sa);
+    }
+
+    // Sum the waves' accumulators in a fixed order.  red[w][band][re, im][row][column]
+    // (16 x 32 per band) reuses the weight tables.
+    __syncthreads();
+    float* red = ws;
+    {
+        const int lane = tid & 63, kq = lane >> 4, i = lane & 15;
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int part = 0; part < 2; ++part)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rc = (4 * kq + v) * 32 + 16 * bj + i;
+                    red[((wv * 2 + 0) * 2 + part) * 512 + rc] = acc0[bj][part][v];
+                    red[((wv * 2 + 1) * 2 + part) * 512 + rc] = acc1[bj][part][v];
+                }
+    }
+    __syncthreads();
+    const int vol = W[0] * W[1];
+    for (int e = tid; e < vol; e += blockDim.x) {
+        const int rho = e / W[1], c = e - rho * W[1];
+        float re = 0.0f, im = 0.0f;
+        if (rho < 16) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                re += red[((w * 2 + 0) * 2 + 0) * 512 + rho * 32 + c];
+                im += red[((w * 2 + 0) * 2 + 1) * 512 + rho * 32 + c];
+            }
+        }
+        if (rho >= S) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                re += red[((w * 2 + 1) * 2 + 0) * 512 + (rho - S) * 32 + c];
+                im += red[((w * 2 + 1) * 2 + 1) * 512 + (rho - S) * 32 + c];
+            }
+        }
+        box_store<float>(a, ci, e, Cx<float>{re, im});
+    }
+}
+
 // d = 3 spreading by box columns.  Thread t owns the box column (c1, c2) = (t div 16,
 // t mod 16) with every c0 in registers, so boxes of at most 16^3 points are covered by 256
 // threads; wave w holds c1 in [4w, 4w + 4).  For a batch of the chunk's nodes, LDS holds
@@ -850,6 +1052,19 @@ KFn spread_rows_m(int m, int rpl) {
     }
 }
 
+KFn spread_mfma2_m(int m) {
+    switch (m) {
+        case 2: return k_spread_mfma2<4>;
+        case 3: return k_spread_mfma2<6>;
+        case 4: return k_spread_mfma2<8>;
+        case 5: return k_spread_mfma2<10>;
+        case 6: return k_spread_mfma2<12>;
+        case 7: return k_spread_mfma2<14>;
+        case 8: return k_spread_mfma2<16>;
+        default: return nullptr;
+    }
+}
+
 template <typename R, int METHOD, bool EXACT>
 KFn spread_rows3_m(int m) {
     switch (m) {
@@ -1233,12 +1448,25 @@ bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes) {
     const bool use_os = !use_rows && !use_rows3 && box <= int64_t(kp) * kOsThreads && os_lds <= 160 * 1024 &&
                         std::getenv("BL_SPREAD_ATOMIC") == nullptr;
     KFn fn;
-    // d = 2 row kernel: box rows per lane (BL_SPREAD_RPL overrides)
-    int rpl = 8;
-    if (const char* e = std::getenv("BL_SPREAD_RPL")) rpl = std::atoi(e) == 4 ? 4 : 8;
+    // d = 2 row kernel: box rows per lane, 4 (eight rows per lane measured slower;
+    // BL_SPREAD_RPL=8 selects them)
+    int rpl = 4;
+    if (const char* e = std::getenv("BL_SPREAD_RPL")) rpl = std::atoi(e) == 8 ? 8 : 4;
     // Double row kernels with closed-form weights are separate instantiations, so that the
     // polynomial ones are not register-sized for them.
     const bool exact = p.prec == BL_F64 && !p.use_poly64;
+    // float d = 2 boxes run on the matrix cores unless BL_SPREAD_ROWS asks for the row kernel
+    const bool use_mfma2 = use_rows && p.prec != BL_F64 && std::getenv("BL_SPREAD_ROWS") == nullptr;
+    if (use_mfma2) {
+        const KFn fp = spread_mfma2_m(p.m);
+        if (!fp) {
+            set_error("no spreading kernel for this (d, m)");
+            return BL_EUNSUPPORTED;
+        }
+        hipLaunchKernelGGL(fp, dim3(unsigned(p.nchunks)), dim3(256), mfma2_lds_bytes(), p.stream, a);
+        BL_HIP(hipGetLastError());
+        return merge();
+    }
     if (use_rows) {
         if (p.prec != BL_F64) fn = p.method == BL_NFFT ? spread_rows_m<float, 1, false>(p.m, rpl) : spread_rows_m<float, 0, false>(p.m, rpl);
         else if (exact) fn = p.method == BL_NFFT ? spread_rows_m<double, 1, true>(p.m, rpl) : spread_rows_m<double, 0, true>(p.m, rpl);

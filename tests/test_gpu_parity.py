@@ -318,17 +318,22 @@ def test_adjoint_matches_oracle(d, M, L, m, N, prec, method):
 
 @pytest.mark.parametrize("d,M,L,m,N,tile", [(1, 64, 128, 5, 1500, None), (2, 32, 64, 6, 40000, None),
                                             (2, 64, 128, 8, 5000, None), (2, 64, 128, 4, 5000, 24),
+                                            (2, 64, 128, 4, 5000, 8), (2, 64, 128, 3, 5000, 11),
+                                            (2, 64, 128, 2, 5000, 14), (2, 64, 128, 6, 5000, 28),
                                             (3, 16, 32, 3, 1500, None), (3, 16, 32, 3, 40000, None),
                                             (3, 32, 64, 4, 12000, None), (3, 32, 64, 2, 12000, 11),
                                             (3, 16, 32, 7, 2000, None)])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("kernel", ["default", "BL_SPREAD_OS", "BL_SPREAD_ATOMIC"])
+@pytest.mark.parametrize("kernel", ["default", "BL_SPREAD_ROWS", "BL_SPREAD_OS", "BL_SPREAD_ATOMIC"])
 def test_adjoint_spread_kernels(d, M, L, m, N, tile, prec, kernel, monkeypatch):
-    """Each spreading kernel (d = 2 and d = 3 row kernels, output-stationary kernel,
-    LDS-atomic kernel) against the oracle, with several node batches per chunk (N = 40000
-    puts about 2500 nodes in each of 16 tiles in d = 2, 625 in each of 64 in d = 3, so
-    also several chunks per tile), boxes that do not fit the d = 2 row kernel (tile 24),
-    and d = 3 boxes of 14^3 (m = 4, tile 7; m = 2, tile 11; FP64 m = 7, tile 1)."""
+    """Each spreading kernel (d = 2 matrix-core kernel for float, d = 2 and d = 3 row
+    kernels, output-stationary kernel, LDS-atomic kernel) against the oracle, with several
+    node batches per chunk (N = 40000 puts about 2500 nodes in each of 16 tiles in d = 2,
+    625 in each of 64 in d = 3, so also several chunks per tile).  d = 2 boxes: 15 x 15
+    and 16 x 16 (one band of rows, tiles 8 and 11), 17 x 17 (two bands one row apart,
+    tile 14, m = 2), 31 x 31 (tile 24), 39 x 39 (tile 28, m = 6: too large for the row and
+    matrix-core kernels).  d = 3 boxes of 14^3 (m = 4, tile 7; m = 2, tile 11; FP64 m = 7,
+    tile 1)."""
     if kernel != "default":
         monkeypatch.setenv(kernel, "1")
     if tile is not None:
