@@ -212,9 +212,9 @@ std::vector<int> coverage_table(const Plan& p, int T) {
         }
         row[1] = n;
     }
-    // the merge's reach flags mark, per box, the distinct tiles of its W coordinates: at most
-    // eight per dimension (kReachList in spread.hip), else the general merge is used
-    for (int t = 0; t < tpd; ++t) {
+    // d = 3: the merge's reach flags mark, per box, the distinct tiles of its W coordinates:
+    // at most eight per dimension (kReachList in spread.hip), else the general merge is used
+    for (int t = 0; t < tpd && p.d == 3; ++t) {
         int distinct = 0, last = -1;
         std::vector<int> seen;
         for (int c = t * T - m + 1; c <= t * T + T + m - 2; ++c) {
@@ -266,7 +266,7 @@ bl_status apply_tiles(Plan& p, int T, int cap) {
     for (int32_t** a : {&p.d_tile_count, &p.d_tile_offset, &p.d_tile_cursor, &p.d_chunk_offset})
         BL_TRY(dev_alloc(a, sizeof(int32_t) * size_t(p.ntiles), &extra));
     BL_TRY(dev_alloc(reinterpret_cast<char**>(&p.d_scan), tile_scan_scratch_bytes(p.ntiles), &extra));
-    BL_TRY(dev_alloc(&p.d_reach, size_t(p.ntiles), &extra));
+    if (p.d == 3) BL_TRY(dev_alloc(&p.d_reach, size_t(p.ntiles), &extra));
     p.tile_alloc = p.ntiles;
     p.workspace_bytes += extra;
     return BL_OK;

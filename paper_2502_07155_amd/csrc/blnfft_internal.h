@@ -183,9 +183,10 @@ struct Plan {
     int32_t* d_tile_cursor = nullptr;
     int32_t* d_chunk_offset = nullptr;
     void* d_scan = nullptr;        // block sums of the tile scans (tile_scan_scratch_bytes)
-    // Adjoint merge tables: per grid coordinate (shared by the dimensions) its tile and the
+    // Adjoint merge table: per grid coordinate (shared by the dimensions) its tile and the
     // (tile offset, box position) pairs of the boxes that cover it (kCovRow ints, up to
-    // kCovMax pairs with offsets within kNbR; null otherwise), and one reach flag per tile.
+    // kCovMax pairs with offsets within kNbR; null otherwise), and for d = 3 one reach flag
+    // per tile.
     int* d_cov = nullptr;
     unsigned char* d_reach = nullptr;
     int4* d_chunks = nullptr;      // {tile, start, count, 0}

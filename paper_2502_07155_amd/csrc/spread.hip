@@ -1110,8 +1110,9 @@ struct MergeArgs {
     const int32_t* chunk_off;    // first chunk of each tile
     const int* cov;              // coverage table, kCovRow ints per coordinate (or null):
                                  // tile of p, count, (tile offset, box position) pairs
-    unsigned char* reach;        // per tile: some non-empty box covers it
     int periodic;                // tile offsets wrap (Algorithm 2.1)
+    int prezeroed;               // the grid was zero-filled before the merge
+    const unsigned char* reach;  // per tile: some non-empty box covers it (null: not marked)
     int64_t box_vol, n;
     int L, m, cap;
     int tile[3], tpd[3], W[3];
@@ -1182,7 +1183,7 @@ __global__ void __launch_bounds__(256) k_box_merge(MergeArgs a) {
     static_cast<Cx<R>*>(a.grid)[gi] = Cx<R>{re, im};
 }
 
-// Per-tile flag: does the box of some non-empty tile cover a point of this tile?  Cleared,
+// Per-tile flag (d = 3): does the box of some non-empty tile cover a point of this tile?  Cleared,
 // then marked from the non-empty tiles: tile t spans box coordinates t T - m + 1 ...
 // t T + T + m - 2 per dimension (wrapped for the periodic sums), and every tile holding
 // one of them is marked (the same value from every writer).  Launched over the tiles as a
@@ -1194,7 +1195,7 @@ __global__ void k_reach_clear(unsigned char* reach, int64_t ntiles) {
 }
 
 template <int D, int METHOD>
-__global__ void __launch_bounds__(256) k_reach_mark(MergeArgs a) {
+__global__ void __launch_bounds__(256) k_reach_mark(MergeArgs a, unsigned char* reach) {
     int tc[3] = {0, 0, 0};
     tc[D - 1] = int(blockIdx.x) * 256 + int(threadIdx.x);
     if (tc[D - 1] >= a.tpd[D - 1]) return;
@@ -1223,30 +1224,32 @@ __global__ void __launch_bounds__(256) k_reach_mark(MergeArgs a) {
         }
     }
     if constexpr (D == 1) {
-        for (int i = 0; i < n[0]; ++i) a.reach[list[0][i]] = 1;
+        for (int i = 0; i < n[0]; ++i) reach[list[0][i]] = 1;
     } else if constexpr (D == 2) {
         for (int i = 0; i < n[0]; ++i)
-            for (int j = 0; j < n[1]; ++j) a.reach[list[0][i] * a.tpd[1] + list[1][j]] = 1;
+            for (int j = 0; j < n[1]; ++j) reach[list[0][i] * a.tpd[1] + list[1][j]] = 1;
     } else {
         for (int i = 0; i < n[0]; ++i)
             for (int j = 0; j < n[1]; ++j)
-                for (int k = 0; k < n[2]; ++k) a.reach[(list[0][i] * a.tpd[1] + list[1][j]) * a.tpd[2] + list[2][k]] = 1;
+                for (int k = 0; k < n[2]; ++k) reach[(list[0][i] * a.tpd[1] + list[1][j]) * a.tpd[2] + list[2][k]] = 1;
     }
 }
 
-// Zero fill of the spreading grid (16-byte stores; n16 of them, then the tail of nbytes).
+// Zero fill of the spreading grid (16-byte stores; n16 of them).
 __global__ void __launch_bounds__(256) k_grid_zero(uint4* g, int64_t n16) {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i < n16) g[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// The merge, one workgroup per tile, after the grid has been zero-filled: a tile that no
-// non-empty box reaches keeps its zeros.  Otherwise the workgroup first stages, for every
-// neighbour offset (dt_0, ..., dt_{d-1}) in [-kNbR, kNbR]^d, the first chunk box of that
-// neighbour and its chunk count (-1 for an empty or absent tile); then every point of the
-// tile is the sum over the (offset, box position) pairs of its coordinates' coverage rows,
-// in row-major order of the pairs and chunk order within a tile (each chunk-box entry is
-// read exactly once, by the one grid point it covers).
+// The merge, one workgroup per tile.  The workgroup first stages, for every neighbour offset
+// (dt_0, ..., dt_{d-1}) in [-kNbR, kNbR]^d, the first chunk box of that neighbour and its
+// chunk count (-1 for an empty or absent tile).  A tile that no non-empty box reaches is
+// written with zeros, or left as it is when the grid was zero-filled before (d = 3, where
+// most tiles of clustered nodes are such tiles and a streaming fill writes them faster than
+// tile by tile); otherwise every point of the tile is
+// the sum over the (offset, box position) pairs of its coordinates' coverage rows, in
+// row-major order of the pairs and chunk order within a tile (each chunk-box entry is read
+// exactly once, by the one grid point it covers).
 template <typename R, int D>
 __global__ void __launch_bounds__(256) k_box_merge_tiles(MergeArgs a) {
     constexpr int NB = 2 * kNbR + 1;
@@ -1254,7 +1257,7 @@ __global__ void __launch_bounds__(256) k_box_merge_tiles(MergeArgs a) {
     __shared__ long long nb[NBV];    // first box of the neighbour tile (-1: none)
     __shared__ int nbc[NBV];         // its chunk count
     const int t = int(blockIdx.x);
-    if (!a.reach[t]) return;
+    if (a.reach && !a.reach[t]) return;   // marked unreached on a zero-filled grid
     int tc[3] = {0, 0, 0}, n0[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
     {
         int r = t;
@@ -1266,6 +1269,7 @@ __global__ void __launch_bounds__(256) k_box_merge_tiles(MergeArgs a) {
             ext[k] = min(a.tile[k], a.L - n0[k]);
         }
     }
+    int reached = 0;   // some neighbour within reach has nodes
     for (int q = threadIdx.x; q < NBV; q += blockDim.x) {
         int rem = q, tt = 0;
         bool ok = true;
@@ -1282,11 +1286,27 @@ __global__ void __launch_bounds__(256) k_box_merge_tiles(MergeArgs a) {
         const int cnt = ok ? a.tile_count[tt] : 0;
         nb[q] = cnt > 0 ? (long long)a.chunk_off[tt] * a.box_vol : -1;
         nbc[q] = (cnt + a.cap - 1) / a.cap;
+        reached = reached || cnt > 0;
     }
-    __syncthreads();
+    reached = __syncthreads_or(reached);   // also the barrier after the tables
     const Cx<R>* __restrict__ boxes = static_cast<const Cx<R>*>(a.boxes);
     Cx<R>* __restrict__ grid = static_cast<Cx<R>*>(a.grid);
     const int vol = ext[0] * ext[1] * ext[2];
+    if (!reached) {
+        if (a.prezeroed) return;
+        for (int e = threadIdx.x; e < vol; e += blockDim.x) {
+            int r = e;
+            int64_t gi = 0, stride = 1;
+#pragma unroll
+            for (int k = D - 1; k >= 0; --k) {
+                gi += (n0[k] + r % ext[k]) * stride;
+                r /= ext[k];
+                stride *= a.L;
+            }
+            grid[gi] = Cx<R>{R(0), R(0)};
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < vol; e += blockDim.x) {
         int p[3] = {0, 0, 0};
         {
@@ -1398,23 +1418,25 @@ bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes) {
         ma.W[t] = p.tile[t] + 2 * p.m - 1;
     }
     ma.cov = p.d_cov;
-    ma.reach = p.d_reach;
     ma.periodic = p.method == BL_NFFT ? 1 : 0;
     auto merge = [&]() -> bl_status {
         KFnM mf;
         if (p.d_cov) {
-            hipLaunchKernelGGL(k_reach_clear, dim3(unsigned((p.ntiles + 255) / 256)), dim3(256), 0, p.stream,
-                               p.d_reach, p.ntiles);
-            const dim3 tg(unsigned((p.tiles_per_dim[p.d - 1] + 255) / 256), p.d >= 2 ? unsigned(p.tiles_per_dim[p.d - 2]) : 1u,
-                          p.d == 3 ? unsigned(p.tiles_per_dim[0]) : 1u);
-            KFnM rf;
-            if (p.method == BL_NFFT) rf = p.d == 1 ? k_reach_mark<1, 1> : p.d == 2 ? k_reach_mark<2, 1> : k_reach_mark<3, 1>;
-            else rf = p.d == 1 ? k_reach_mark<1, 0> : p.d == 2 ? k_reach_mark<2, 0> : k_reach_mark<3, 0>;
-            hipLaunchKernelGGL(rf, tg, dim3(256), 0, p.stream, ma);
-            const int64_t bytes = p.grid_elems() * int64_t(p.cplx_size());   // a multiple of 16 (L even)
-            hipLaunchKernelGGL(k_grid_zero, dim3(unsigned((bytes / 16 + 255) / 256)), dim3(256), 0, p.stream,
-                               static_cast<uint4*>(grid), bytes / 16);
-            BL_HIP(hipGetLastError());
+            if (p.d == 3 && p.d_reach) {
+                // clustered d = 3 nodes leave most tiles unreached: mark the reached ones from
+                // the non-empty tiles and zero-fill the grid first
+                hipLaunchKernelGGL(k_reach_clear, dim3(unsigned((p.ntiles + 255) / 256)), dim3(256), 0, p.stream,
+                                   p.d_reach, p.ntiles);
+                const dim3 tg(unsigned((p.tiles_per_dim[2] + 255) / 256), unsigned(p.tiles_per_dim[1]),
+                              unsigned(p.tiles_per_dim[0]));
+                void (*rf)(MergeArgs, unsigned char*) = p.method == BL_NFFT ? k_reach_mark<3, 1> : k_reach_mark<3, 0>;
+                hipLaunchKernelGGL(rf, tg, dim3(256), 0, p.stream, ma, p.d_reach);
+                const int64_t bytes = p.grid_elems() * int64_t(p.cplx_size());   // a multiple of 16 (L even)
+                hipLaunchKernelGGL(k_grid_zero, dim3(unsigned((bytes / 16 + 255) / 256)), dim3(256), 0, p.stream,
+                                   static_cast<uint4*>(grid), bytes / 16);
+                ma.prezeroed = 1;
+                ma.reach = p.d_reach;
+            }
             mf = p.prec == BL_F64 ? merge_tiles_d<double>(p.d) : merge_tiles_d<float>(p.d);
             hipLaunchKernelGGL(mf, dim3(unsigned(p.ntiles)), dim3(256), 0, p.stream, ma);
             BL_HIP(hipGetLastError());
