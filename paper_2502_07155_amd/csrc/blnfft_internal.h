@@ -209,7 +209,7 @@ struct Plan {
         void* f = nullptr;
         uint64_t used = 0;
     };
-    bool use_graph = true;
+    bool use_graph = false;   // BL_GRAPH=1: forward transforms replay a captured graph
     hipStream_t capture_stream = nullptr;
     FwdGraph graphs[kGraphCache];
     uint64_t graph_tick = 0;

@@ -443,7 +443,11 @@ def test_graph_replays_match_eager_launches():
         eager = make_plan(p, "f32c")
     finally:
         del os.environ["BL_GRAPH"]
-    graph = make_plan(p, "f32c")
+    os.environ["BL_GRAPH"] = "1"
+    try:
+        graph = make_plan(p, "f32c")
+    finally:
+        del os.environ["BL_GRAPH"]
     x = dev_real(p.x, "f32c")
     fh = dev_cplx(p.fhat, "f32c")
     eager.set_nodes(x)
