@@ -324,9 +324,12 @@ __global__ void k_chunk_fill(const int32_t* count, const int32_t* offset,
 }
 
 // Within one chunk, order the nodes by their cell inside the tile (row-major), so that
-// neighbouring lanes of the short-sum kernel read neighbouring samples from LDS.  LDS
-// counting sort over the tile's cells; the chunk's sorted nodes and permutation are
-// rewritten in place (all reads complete before the first write).
+// neighbouring lanes of the short-sum kernel read neighbouring samples from LDS, and the
+// nodes of one cell by their index in the caller's order: the order inside a chunk then
+// depends only on the chunk's nodes, not on the order the binning scatter left them in.
+// LDS counting sort over the tile's cells, then each node's rank among its cell's nodes
+// from their caller indices; the chunk's sorted nodes and permutation are rewritten in
+// place (all reads complete before the first write).
 constexpr int kSortPerThread = 4;   // chunk_cap / 256
 
 struct SortArgs {
@@ -401,6 +404,21 @@ __global__ void __launch_bounds__(256) k_chunk_sort(SortArgs a) {
         run += c;
     }
     __syncthreads();
+    // the caller indices of each cell's nodes, in arrival order, then every node's rank
+    // among them by caller index (caller indices are distinct)
+    __shared__ int bucket[kSortPerThread * 256];
+#pragma unroll
+    for (int q = 0; q < kSortPerThread; ++q)
+        if (key[q] >= 0) bucket[hist[key[q]] + rank[q]] = pv[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSortPerThread; ++q) {
+        if (key[q] < 0) continue;
+        const int s0 = hist[key[q]], s1 = key[q] + 1 < tvol ? hist[key[q] + 1] : ch.z;
+        int r = 0;
+        for (int e = s0; e < s1; ++e) r += bucket[e] < pv[q] ? 1 : 0;
+        rank[q] = r;
+    }
 #pragma unroll
     for (int q = 0; q < kSortPerThread; ++q) {
         if (key[q] < 0) continue;
