@@ -1322,7 +1322,51 @@ __global__ void __launch_bounds__(256) k_box_merge_tiles(MergeArgs a) {
         const int* r2 = a.cov + p[D == 3 ? 2 : 0] * kCovRow;
         const int n0c = r0[1], n1c = D >= 2 ? r1[1] : 1, n2c = D == 3 ? r2[1] : 1;
         R re = R(0), im = R(0);
-        for (int i = 0; i < n0c; ++i) {
+        // At most two covering boxes per coordinate, none of a tile with several chunks
+        // (decided from the staged tables before any box is read): every read is issued
+        // before the first add, and the terms are summed in the order of the general loop
+        // below (an absent term adds +0, which changes no sum that starts at +0), so both
+        // forms give the same bits.
+        bool done = false;
+        if (n0c <= 2 && n1c <= 2 && n2c <= 2) {
+            constexpr int K1 = D >= 2 ? 2 : 1, K2 = D == 3 ? 2 : 1, K = 2 * K1 * K2;
+            int slot[K], be[K];
+            bool single = true;   // every present covering tile has one chunk
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < K1; ++j)
+#pragma unroll
+                    for (int k = 0; k < K2; ++k) {
+                        const int q = (i * K1 + j) * K2 + k;
+                        slot[q] = -1;
+                        be[q] = 0;
+                        if (i < n0c && j < n1c && k < n2c) {
+                            const int o0 = r0[2 + 2 * i] + kNbR, c0 = r0[3 + 2 * i];
+                            const int o1 = D >= 2 ? r1[2 + 2 * j] + kNbR : 0, c1 = D >= 2 ? r1[3 + 2 * j] : 0;
+                            const int o2 = D == 3 ? r2[2 + 2 * k] + kNbR : 0, c2 = D == 3 ? r2[3 + 2 * k] : 0;
+                            slot[q] = D == 1 ? o0 : D == 2 ? o0 * NB + o1 : (o0 * NB + o1) * NB + o2;
+                            be[q] = D == 1 ? c0 : D == 2 ? c0 * a.W[1] + c1 : (c0 * a.W[1] + c1) * a.W[2] + c2;
+                            single = single && nbc[slot[q]] <= 1;
+                        }
+                    }
+            if (single) {
+                Cx<R> v[K];
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    v[q] = Cx<R>{R(0), R(0)};
+                    const long long base = slot[q] >= 0 ? nb[slot[q]] : -1;
+                    if (base >= 0) v[q] = boxes[base + be[q]];
+                }
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    re += v[q].re;
+                    im += v[q].im;
+                }
+                done = true;
+            }
+        }
+        for (int i = 0; i < (done ? 0 : n0c); ++i) {
             const int o0 = r0[2 + 2 * i] + kNbR, c0 = r0[3 + 2 * i];
             for (int j = 0; j < n1c; ++j) {
                 const int o1 = D >= 2 ? r1[2 + 2 * j] + kNbR : 0, c1 = D >= 2 ? r1[3 + 2 * j] : 0;
@@ -1334,6 +1378,7 @@ __global__ void __launch_bounds__(256) k_box_merge_tiles(MergeArgs a) {
                     const long long base = nb[slot];
                     if (base >= 0) {
                         const int nch = nbc[slot];
+#pragma unroll 4
                         for (int c = 0; c < nch; ++c) {   // the tile's chunks in order
                             const Cx<R> v = boxes[base + int64_t(c) * a.box_vol + be];
                             re += v.re;
