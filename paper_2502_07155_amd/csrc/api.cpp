@@ -276,7 +276,7 @@ bl_status apply_tiles(Plan& p, int T, int cap) {
 double time_gather(Plan& p, void* f, hipEvent_t e0, hipEvent_t e1) {
     if (launch_gather(p, p.d_grid, f) != BL_OK) return -1.0;
     if (hipEventRecord(e0, p.stream) != hipSuccess) return -1.0;
-    constexpr int reps = 3;
+    constexpr int reps = 10;
     for (int r = 0; r < reps; ++r)
         if (launch_gather(p, p.d_grid, f) != BL_OK) return -1.0;
     float ms = 0.0f;
@@ -288,9 +288,13 @@ double time_gather(Plan& p, void* f, hipEvent_t e0, hipEvent_t e1) {
 
 // Node binning with the autotuned tile edge and chunk capacity: the nodes are binned with
 // the default tiles first, which classifies them (nodes per grid point, fullest tile
-// against the mean); a cached choice for that class is applied, or every candidate is
-// timed and the fastest kept and cached.  A later binning of as many nodes keeps the
-// plan's choice.
+// against the mean); a cached choice for that class is applied, or every candidate's short
+// sums are timed and the choice cached: among the candidates within kTileTie of the
+// fastest (the spread of repeated timings), the one with the fewest work chunks, since the
+// adjoint writes and merges one box per chunk.  A later binning of as many nodes keeps
+// the plan's choice.
+constexpr double kTileTie = 0.015;
+
 bl_status bin_tuned(Plan& p, const void* x, int64_t N) {
     if (!tile_tuning_wanted(p, N) || (p.tuned_N == N && p.tune_tile_source != 0))
         return launch_binning(p, x, N);
@@ -320,19 +324,30 @@ bl_status bin_tuned(Plan& p, const void* x, int64_t N) {
             st = fail(BL_EDEVICE, "autotuner: event or memset failed");
         }
         double best_ms = -1.0;
+        std::vector<double> ms_of(cands.size(), -1.0);
+        std::vector<int64_t> chunks_of(cands.size(), 0);
         for (size_t i = 0; st == BL_OK && i < cands.size(); ++i) {
             st = apply_tiles(p, cands[i].first, cands[i].second);
             if (st == BL_OK) st = launch_binning(p, x, N);
             if (st != BL_OK) break;
             const double ms = time_gather(p, f, e0, e1);
+            ms_of[i] = ms;
+            chunks_of[i] = p.nchunks;
             if (std::getenv("BL_TUNE_VERBOSE"))
                 std::fprintf(stderr, "blnfft tune tiles: d=%d L=%lld m=%d tile=%d cap=%d chunks=%lld: %.2f us\n", p.d,
                              (long long)p.L, p.m, cands[i].first, cands[i].second, (long long)p.nchunks, ms * 1e3);
-            if (ms > 0.0 && (best_ms < 0.0 || ms < best_ms)) {
-                best_ms = ms;
-                T = cands[i].first;
-                cap = cands[i].second;
-            }
+            if (ms > 0.0 && (best_ms < 0.0 || ms < best_ms)) best_ms = ms;
+        }
+        size_t pick = cands.size();
+        for (size_t i = 0; best_ms > 0.0 && i < cands.size(); ++i) {
+            if (!(ms_of[i] > 0.0 && ms_of[i] <= best_ms * (1.0 + kTileTie))) continue;
+            if (pick == cands.size() || chunks_of[i] < chunks_of[pick] ||
+                (chunks_of[i] == chunks_of[pick] && ms_of[i] < ms_of[pick]))
+                pick = i;
+        }
+        if (pick < cands.size()) {
+            T = cands[pick].first;
+            cap = cands[pick].second;
         }
         (void)hipStreamSynchronize(p.stream);
         if (e0) hipEventDestroy(e0);

@@ -431,6 +431,31 @@ def test_adjoint_is_bitwise_repeatable(name, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32c"])
+def test_adjoint_mixed_dense_and_sparse_tiles(prec):
+    """d = 2 adjoint where single-chunk tiles border a tile of many chunks (a cluster of
+    6000 nodes inside 4000 uniform ones), so one merge both reads single-chunk covering
+    boxes together and sums multi-chunk ones chunk by chunk; against the oracle and bitwise
+    repeatable."""
+    from paper_2502_07155_amd import Plan
+    d, M, L, m = 2, 64, 128, 4
+    rng = W.rng_for(17)
+    x = np.concatenate([rng.random((4000, d)) - 0.5, 0.1 + 0.02 * rng.random((6000, d))])
+    y = W.complex_normal(rng, (x.shape[0],))
+    if prec != "f64":
+        x = x.astype(np.float32).astype(np.float64)
+        y = y.astype(np.complex64).astype(np.complex128)
+    plan = Plan(d, M, L, m, precision=prec)
+    plan.set_nodes(dev_real(x, prec))
+    assert plan.stats()["n_chunks"] >= 64 + 5
+    yd = dev_cplx(y, prec)
+    a = host(plan.adjoint(yd))
+    assert np.array_equal(a, host(plan.adjoint(yd)))
+    ao = O.adjoint_shannon(y, x, M, L, m)
+    assert O.rel_err_inf(a, ao) <= (1e-12 if prec == "f64" else 1e-5)
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_adjoint_bits_survive_rebinding_when_tiles_fit_one_chunk(prec):
     """With at most one work chunk per tile (~195 uniform nodes per 16^2 tile here), the
