@@ -294,12 +294,14 @@ double time_gather(Plan& p, void* f, hipEvent_t e0, hipEvent_t e1) {
 // adjoint writes and merges one box per chunk.  A later binning of as many nodes keeps
 // the plan's choice.
 constexpr double kTileTie = 0.015;
+constexpr int kDefaultChunk = 1024;   // nodes per work chunk without tuning
+constexpr int kSmallChunk = 256;     // the same below kTuneMinNodes nodes
 
 bl_status bin_tuned(Plan& p, const void* x, int64_t N) {
     if (!tile_tuning_wanted(p, N) || (p.tuned_N == N && p.tune_tile_source != 0))
         return launch_binning(p, x, N);
     p.N = N;   // the short-sum kernel timed below runs over p.N nodes
-    BL_TRY(apply_tiles(p, default_tile(p), 1024));
+    BL_TRY(apply_tiles(p, default_tile(p), kDefaultChunk));
     BL_TRY(launch_binning(p, x, N));
     std::vector<int32_t> cnt(size_t(p.ntiles));
     BL_HIP(hipMemcpy(cnt.data(), p.d_tile_count, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost));
@@ -627,7 +629,7 @@ bl_status bl_plan_create(bl_plan* out, int d, int64_t M, int64_t L, int m, bl_wi
             return cleanup(s);
     }
     p.dual_tiles = dual_tiles_for(d, p.m, p.prec != BL_F64);
-    if ((s = apply_tiles(p, default_tile(p), 1024)) != BL_OK) return cleanup(s);
+    if ((s = apply_tiles(p, default_tile(p), kDefaultChunk)) != BL_OK) return cleanup(s);
     if ((s = dev_alloc(&p.d_flags, sizeof(unsigned long long) * 4, &total)) != BL_OK) return cleanup(s);
     p.workspace_bytes += total;
 
@@ -668,6 +670,14 @@ bl_status bl_set_nodes(bl_plan plan, int64_t N, const void* x_dev) {
         p.d_wpre = nullptr;
     }
     p.use_wpre = false;
+    // Bindings the tile tuning does not time take chunks of at most kSmallChunk nodes below
+    // kTuneMinNodes nodes (one node per thread of a short-sum workgroup, so that a few
+    // thousand nodes occupy several workgroups instead of one looping over them), else
+    // kDefaultChunk.
+    if (!tile_tuning_wanted(p, N)) {
+        const int want = N < kTuneMinNodes ? kSmallChunk : kDefaultChunk;
+        if (want != p.chunk_cap) BL_TRY(apply_tiles(p, p.tile[0], want));
+    }
     // work chunks: at most N / cap + ntiles + 1 for the current tiles and every candidate
     // of the autotuner
     int64_t chunk_bound = N / p.chunk_cap + p.ntiles + 1;
