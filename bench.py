@@ -71,8 +71,9 @@ def parse():
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="print a kernel's HBM traffic per launch from four rocprofv3 --pmc "
                          "csv output directories and exit (no GPU use)")
-    ap.add_argument("--traffic-kernel", default="gather", choices=["gather", "fft"],
-                    help="with --summarize-traffic: the gather, or the FFT passes of a transform")
+    ap.add_argument("--traffic-kernel", default="gather", choices=["gather", "fft", "spread", "merge"],
+                    help="with --summarize-traffic: the gather, the FFT passes of a transform, or the "
+                         "adjoint's spreading or box-merge kernel")
     ap.add_argument("--traffic-passes", type=int, default=1,
                     help="with --summarize-traffic: dispatches per launch (FFT: one per dimension)")
     return ap.parse_args()
@@ -177,6 +178,7 @@ def measured_traffic():
 
 
 FFT_SOURCES = ["paper_2502_07155_amd/csrc/fft.hip", "paper_2502_07155_amd/csrc/stockham.h"]
+SPREAD_SOURCES = ["paper_2502_07155_amd/csrc/spread.hip", "paper_2502_07155_amd/csrc/device_math.h"]
 
 
 def measured_fft_traffic(workload: str, prec: str):
@@ -770,11 +772,15 @@ def _counter_per_dispatch(directory: str, keep):
 
 def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel: str = "gather",
                       per_launch: int = 1) -> str:
-    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the gather (kernel "gather") or of the
-    FFT passes (kernel "fft": per_launch passes per transform, summed), each divided by the
-    counter-to-bytes factor of a 1 GiB device copy (which reads and writes 1 GiB)."""
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the gather (kernel "gather"), of the
+    FFT passes (kernel "fft": per_launch passes per transform, summed) or of the adjoint's
+    spreading ("spread") or box-merge ("merge") kernel, each divided by the counter-to-bytes
+    factor of a 1 GiB device copy (which reads and writes 1 GiB)."""
+    marks = {"gather": ("k_gather<",), "fft": ("k_fft_pass<", "k_czt_pass<"),
+             "spread": ("k_spread",), "merge": ("k_box_merge",)}[kernel]
+
     def pick(name):
-        return ("k_gather<" in name) if kernel == "gather" else ("k_fft_pass<" in name or "k_czt_pass<" in name)
+        return any(k in name for k in marks)
 
     def copy(name):
         return True   # the calibration run launches nothing but the copies
@@ -786,7 +792,7 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kern
     gib_kib = float(1 << 20)
     ff, fw = cf / gib_kib, cw / gib_kib
     traffic = (fetch / ff + write / fw) * 1024.0 * per_launch
-    sources = GATHER_SOURCES if kernel == "gather" else FFT_SOURCES
+    sources = {"gather": GATHER_SOURCES, "fft": FFT_SOURCES}.get(kernel, SPREAD_SOURCES)
     return "\n".join([
         f"{kernel}_fetch_kib_per_dispatch: {fetch:.1f}  (dispatches: {nf})",
         f"{kernel}_write_kib_per_dispatch: {write:.1f}  (dispatches: {nw})",
