@@ -1311,6 +1311,7 @@ __global__ void __launch_bounds__(256) k_box_merge_tiles(MergeArgs a) {
         }
         return;
     }
+#pragma unroll 2
     for (int e = threadIdx.x; e < vol; e += blockDim.x) {
         int p[3] = {0, 0, 0};
         {
@@ -1487,7 +1488,10 @@ bl_status launch_spread(Plan& p, const void* g, void* grid, void* boxes) {
                 ma.reach = p.d_reach;
             }
             mf = p.prec == BL_F64 ? merge_tiles_d<double>(p.d) : merge_tiles_d<float>(p.d);
-            hipLaunchKernelGGL(mf, dim3(unsigned(p.ntiles)), dim3(256), 0, p.stream, ma);
+            // d = 2: two points per thread (128 threads for a 16 x 16 tile), so that every
+            // tile of a CU's share is resident at once
+            const unsigned nt = p.d == 2 ? 128u : 256u;
+            hipLaunchKernelGGL(mf, dim3(unsigned(p.ntiles)), dim3(nt), 0, p.stream, ma);
             BL_HIP(hipGetLastError());
             return BL_OK;
         } else {
