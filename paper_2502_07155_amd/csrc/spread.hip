@@ -1311,7 +1311,6 @@ __global__ void __launch_bounds__(256) k_box_merge_tiles(MergeArgs a) {
         }
         return;
     }
-#pragma unroll 2
     for (int e = threadIdx.x; e < vol; e += blockDim.x) {
         int p[3] = {0, 0, 0};
         {
